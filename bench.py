@@ -1,0 +1,176 @@
+"""Benchmark of the fused D3Q19 MRT pseudopotential step on one MI355X.
+
+Default workload: the 256^3 periodic two-droplet precision study (C-S EOS at
+T = 0.6 T_c, a = 0.25, droplets of radius 30 approaching at 0.05), FP32
+population storage, non-orthogonal operator.  One step = one lattice update
+of every node (all of the fused kernel's work).  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage f32|f16s|f64]
+                  [--op nonorth|orth] [--no-cpu] [--no-variants]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS + % of HBM roofline; FP32/FP16-storage vs FP64 at stated error"
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+WORKLOAD = "two_droplets_256"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16s", "f64"])
+    ap.add_argument("--op", default="nonorth", choices=["nonorth", "orth"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def make_lattice(storage, op):
+    import lbm_inputs as li
+    from paper_1805_08643_amd import tuning
+    from paper_1805_08643_amd.binding import Lattice
+    cfg, init = li.c3_two_droplets(op=op)
+    cfg = dict(cfg, storage=storage, rho_ref=init["rho_V"])
+    lat = Lattice(cfg, "cuda:0")
+    tile = tuning.tile_for(WORKLOAD, storage)
+    if tile:
+        lat.set_tile(*tile)
+    lat.init_droplets(init["droplets"], init["rho_L"], init["rho_V"], init["W"])
+    return lat, cfg, init
+
+
+def time_steps(lat, steps, warmup, kernel_timing):
+    import torch
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    if kernel_timing:
+        lat.set_timing(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    lat.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    kms = None
+    if kernel_timing:
+        kms, n = lat.kernel_time()
+        assert n == steps, (n, steps)
+        lat.set_timing(False)
+    return ms, wall, kms
+
+
+def read_traffic(storage, op):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it covers this kernel; None otherwise."""
+    path = os.path.join(ROOT, "profiles", f"step_{WORKLOAD}_{storage}_{op}_pmc.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    return float(m.group(1)) if m else None
+
+
+def cpu_baseline(cfg, init, budget_s):
+    import numpy as np
+
+    import lbm_inputs as li
+    from oracle import ref
+    threads = min(16, os.cpu_count() or 1)
+    p = ref.make_params(cfg, nthreads=threads)
+    rho, u = li.init_fields(cfg, init)
+    f = ref.equilibrium(p, rho, u)
+    N = rho.size
+    t0 = time.perf_counter()
+    f = ref.step(p, f, 1)
+    dt1 = time.perf_counter() - t0
+    extra = max(0, int(budget_s / max(dt1, 1e-9)) - 1)
+    t0 = time.perf_counter()
+    if extra:
+        f = ref.step(p, f, extra)
+    dt = time.perf_counter() - t0
+    steps = extra if extra else 1
+    sec = dt if extra else dt1
+    assert np.isfinite(f).all()
+    return {"value": N * steps / sec / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"full {cfg['nx']}x{cfg['ny']}x{cfg['nz']} lattice, FP64 dense-matrix oracle, "
+                      f"{steps} step(s) after 1 untimed step"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(2)
+    from paper_1805_08643_amd.binding import algorithmic_bytes_per_node
+
+    lat, cfg, init = make_lattice(a.storage, a.op)
+    N = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    ms, wall, kms = time_steps(lat, a.steps, a.warmup, kernel_timing=True)
+    diag = lat.diagnostics()
+    tile = lat.get_tile()
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    ms_step = ms / a.steps
+    mlups = N / (ms_step * 1e-3) / 1e6
+    bpn = algorithmic_bytes_per_node(a.storage)
+    achieved = bpn * N / (kms * 1e-3) / 1e9
+    traffic = read_traffic(a.storage, a.op)
+    out = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if a.storage == "f64" else "f32", "data": "synthetic",
+        "config": {"workload": f"{WORKLOAD}: 256^3 periodic, two droplets r0=30 approaching at 0.05, "
+                               f"C-S T=0.6Tc a=0.25, sigma=0.105",
+                   "storage": a.storage, "op": a.op, "nodes": N, "tile": list(tile)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                     "kernel": "k_step (fused psi/force + collide + pull-stream)",
+                     "kernel_ms": round(kms, 5), "algorithmic_bytes_per_node": bpn},
+        "mass": diag["mass"], "nonfinite": diag["nonfinite"],
+    }
+    if not a.no_variants:
+        var = {}
+        for st, op in [("f16s", "nonorth"), ("f32", "orth"), ("f64", "nonorth"), ("f32", "nonorth")]:
+            if (st, op) == (a.storage, a.op):
+                var[f"{st}_{op}"] = round(mlups, 1)
+                continue
+            l2, c2, _ = make_lattice(st, op)
+            m2, _, k2 = time_steps(l2, max(50, a.steps // 4), 10, kernel_timing=True)
+            var[f"{st}_{op}"] = round(N / (m2 / max(50, a.steps // 4) * 1e-3) / 1e6, 1)
+            var[f"{st}_{op}_hbm_frac"] = round(algorithmic_bytes_per_node(st) * N / (k2 * 1e-3) / 1e9
+                                               / PEAK_HBM_GBS, 4)
+            l2.close()
+            del l2
+            torch.cuda.empty_cache()
+        out["variants_mlups"] = var
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cfg, init, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,220 @@
+/*
+ * mrt_lbm.h -- C ABI of the MI355X (gfx950) library for the D3Q19
+ * non-orthogonal multiple-relaxation-time lattice Boltzmann step with the
+ * pseudopotential multiphase force (Li, Du, Fei, Luo & Yu, arXiv:1805.08643).
+ *
+ * Model, in the paper's notation (Sec. II):
+ *   lattice velocities e_a of Eq. (2); variable fbar = f - G/2 of Eq. (3);
+ *   moments m = M fbar with the non-orthogonal M of Eq. (12) (basis
+ *   Eqs. (7)-(10)); relaxation m* = m - Lambda (m - m_eq) + (I - Lambda/2) S
+ *   (Eq. (4)) with Lambda of Eq. (11), m_eq of Eq. (13), S of Eq. (14) and the
+ *   thermodynamic-consistency term of Eq. (16); fbar* = M^-1 m*; streaming
+ *   Eq. (5); density and velocity Eq. (6); interaction force Eq. (15) with the
+ *   square-root pseudopotential on the Carnahan-Starling EOS of Eq. (58) or
+ *   the exponential pseudopotential; wetting ghost layer Eq. (57).
+ *   The orthogonal Gram-Schmidt operator the paper compares against is
+ *   selected by LBM_OP_ORTH.
+ *
+ * Conventions
+ *   - Lattice units: dt = dx = c = 1, c_s^2 = 1/3.
+ *   - Node index i = (z * ny + y) * nx + x, x fastest.  Per-node fields are
+ *     flat arrays of N = nx*ny*nz doubles; vector fields are three such
+ *     planes back to back (x, y, z components: "SoA").
+ *   - Populations in the canonical form are fbar_a(x, t) after streaming,
+ *     stored f[a * N + i] for a = 0..18 in the order of Eq. (2).
+ *   - Every pointer argument named dev_* or documented as "device" is a
+ *     device (HBM) pointer, typically a torch tensor's data_ptr(); the caller
+ *     owns it.  Host pointers are documented as such.
+ *   - All work is enqueued on the HIP stream given at creation and is
+ *     asynchronous unless stated ("synchronises").
+ *   - Functions return lbm_status.  Parameters are validated before any HIP
+ *     call; on error nothing is launched and lbm_last_error() (thread-local)
+ *     holds a message.  No C++ exception crosses this boundary.
+ */
+#ifndef MRT_LBM_H
+#define MRT_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lbm_status;
+enum {
+    LBM_OK = 0,
+    LBM_ERR_INVALID_ARG = -1,      /* parameter out of range, null pointer */
+    LBM_ERR_BUFFER_TOO_SMALL = -2, /* workspace or buffer smaller than required */
+    LBM_ERR_HIP = -3,              /* a HIP runtime call failed */
+    LBM_ERR_NONFINITE = -4,        /* diagnostics found a NaN/Inf population */
+    LBM_ERR_UNSUPPORTED = -5       /* valid request this build does not implement */
+};
+
+/* Collision operator. */
+enum { LBM_OP_NONORTH = 0, /* Eqs. (7)-(14), (16): the paper's model */
+       LBM_OP_ORTH = 1     /* Gram-Schmidt orthogonal D3Q19 basis (comparison) */ };
+
+/* Population storage in HBM.  Arithmetic is FP64 for F64 storage and FP32
+ * otherwise.  F16S stores h_a = fbar*_a - w_a rho_ref in IEEE binary16
+ * (round to nearest even) with w = 1/3, 1/18, 1/36 by velocity class. */
+enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16S = 2 };
+
+/* Pseudopotential form (text after Eq. (15)). */
+enum { LBM_PSI_SQRT_CS = 0, /* psi = sqrt(2 (p_EOS - rho/3) / G), C-S p_EOS, Eq. (58) */
+       LBM_PSI_EXP = 1      /* psi = psi0 exp(-rho0 / rho) */ };
+
+typedef struct lbm_params {
+    int32_t nx, ny, nz;     /* lattice size, each >= 1 (nz >= 2 with walls) */
+    int32_t wall_z;         /* 0: periodic in z; 1: half-way bounce-back walls at
+                               z = -1/2 and z = nz - 1/2 (x, y always periodic) */
+    int32_t op;             /* LBM_OP_* */
+    int32_t storage;        /* LBM_STORE_* */
+    int32_t psi_form;       /* LBM_PSI_* */
+    int32_t reserved0;      /* must be 0 */
+    double rho_ref;         /* F16S shift density (ignored otherwise) */
+    /* Relaxation rates, Eq. (11); each in (0, 2).  ORTH also uses s_eps (energy
+     * square) and s_m (cubic m_x,y,z rows). */
+    double s_e, s_nu, s_q, s_pi, s_eps, s_m;
+    double G;               /* interaction strength, Eq. (15); < 0 for SQRT_CS */
+    double eos_a, eos_b, eos_R; /* C-S constants, Eq. (58) */
+    double T_over_Tc;       /* T = T_over_Tc * 0.37733 a / (b R) */
+    double psi0, rho0;      /* exponential form constants */
+    double sigma;           /* Eq. (16) constant */
+    double gravity[3];      /* body acceleration g; body force rho g */
+    double theta_wall_deg;  /* prescribed contact angle theta_a, Eq. (57) */
+    double ghost_rho_min;   /* lower clamp of the Eq. (57) ghost density */
+} lbm_params;
+
+/* Launch shape of the fused step: tx * ty threads per block, one thread per
+ * (x, y) column of a tx x ty tile, marching cz planes in z. */
+typedef struct lbm_tile {
+    int32_t tx, ty, cz, reserved;
+} lbm_tile;
+
+/* One droplet of the Eq. (59) initial condition. */
+typedef struct lbm_droplet {
+    double center[3];
+    double r0;
+    double u[3];            /* velocity scaled by the liquid fraction */
+} lbm_droplet;
+
+/* Region selection for the Laplace-law sums: "inside" is |x - c| < r_in,
+ * "outside" is |x - c| > r_out (minimum-image distance on periodic axes). */
+typedef struct lbm_diag_request {
+    double center[3];
+    double r_in, r_out;
+} lbm_diag_request;
+
+typedef struct lbm_diag {
+    double mass;            /* sum rho (FP64) */
+    double momentum[3];     /* sum (sum_a e_a fbar_a + F/2) (FP64) */
+    double max_u;           /* max |u| */
+    double p_in, p_out;     /* sums of p = rho/3 + G psi^2/2 in the two regions */
+    double rho_in, rho_out; /* sums of rho in the two regions */
+    double n_in, n_out;     /* node counts of the two regions */
+    int64_t nonfinite;      /* populations that are NaN or Inf */
+    int64_t step;           /* time steps taken so far */
+} lbm_diag;
+
+typedef struct lbm_ctx lbm_ctx;
+typedef struct lbm_batch lbm_batch;
+
+/* Paper defaults: c_s^2 = 1/3 implied; conserved rates 1; C-S b = 4, R = 1,
+ * a = 0.5; G = -1; sigma = 0; theta = 90 deg; F32 storage, non-orthogonal,
+ * periodic.  nx = ny = nz = 32.  Rates s_e = s_nu = s_q = s_pi = s_eps =
+ * s_m = 1. */
+void lbm_params_default(lbm_params *p);
+
+/* Device bytes needed by lbm_create for these parameters: two population
+ * buffers of 19 N elements, a psi buffer of N, wall planes and diagnostics
+ * partials, each 256-byte aligned. */
+lbm_status lbm_workspace_bytes(const lbm_params *p, size_t *bytes);
+
+/* Create a lattice on the current device.  dev_ws: device buffer of at least
+ * lbm_workspace_bytes bytes, owned by the caller and kept alive until
+ * lbm_destroy.  hip_stream: a hipStream_t (may be NULL = default stream),
+ * borrowed.  The library allocates host memory only.  Populations are left
+ * undefined until an init call. */
+lbm_status lbm_create(const lbm_params *p, void *dev_ws, size_t ws_bytes, void *hip_stream,
+                      lbm_ctx **out);
+lbm_status lbm_destroy(lbm_ctx *ctx);
+
+/* fbar(x, 0) = M^-1 m_eq(rho(x), u(x)) (Eq. (13)), i.e. the equilibrium of
+ * the chosen operator.  rho: device, N doubles; u: device, 3N doubles. */
+lbm_status lbm_init_fields(lbm_ctx *ctx, const double *rho, const double *u);
+
+/* Same, with rho and u from the Eq. (59) tanh profile of each droplet
+ * (host array of n <= 8): at each node the droplet with the largest profile
+ * gives rho, and u = u_d (rho - rho_V) / (rho_L - rho_V). */
+lbm_status lbm_init_droplets(lbm_ctx *ctx, const lbm_droplet *d, int32_t n, double rho_L,
+                             double rho_V, double W);
+
+/* Advance nsteps time steps (asynchronous). */
+lbm_status lbm_step(lbm_ctx *ctx, int64_t nsteps);
+
+/* Macroscopic fields of the current state, Eq. (6): rho (N), u (3N),
+ * p = rho/3 + G psi^2/2 (N); device FP64 outputs, any may be NULL. */
+lbm_status lbm_read_fields(lbm_ctx *ctx, double *rho, double *u, double *p);
+
+/* Canonical populations fbar_a(x, t) (19 N device doubles) out / in. */
+lbm_status lbm_read_populations(lbm_ctx *ctx, double *f);
+lbm_status lbm_write_populations(lbm_ctx *ctx, const double *f);
+
+/* FP64 global sums (see lbm_diag).  req may be NULL (no Laplace sums).
+ * out: host pointer.  Synchronises the stream.  Returns LBM_ERR_NONFINITE
+ * (with out filled) when any population is not finite. */
+lbm_status lbm_diagnostics(lbm_ctx *ctx, const lbm_diag_request *req, lbm_diag *out);
+
+/* Raw state (storage-format populations plus the step counter) to/from a
+ * device buffer of lbm_state_bytes bytes; resuming is bit-identical. */
+lbm_status lbm_state_bytes(const lbm_ctx *ctx, size_t *bytes);
+lbm_status lbm_save_state(lbm_ctx *ctx, void *dev_buf, size_t bytes);
+lbm_status lbm_load_state(lbm_ctx *ctx, const void *dev_buf, size_t bytes);
+
+/* Launch shape.  set validates (tx in [1, 1024], tx * ty <= 1024, cz >= 1,
+ * halo ring 2 (tx + ty) + 4 <= tx * ty).  autotune times `trials` steps of
+ * each candidate shape (output written to the scratch buffer only, so the
+ * state is unchanged), keeps the fastest, and reports it.  Synchronises. */
+lbm_status lbm_set_tile(lbm_ctx *ctx, const lbm_tile *t);
+lbm_status lbm_get_tile(const lbm_ctx *ctx, lbm_tile *t);
+lbm_status lbm_autotune(lbm_ctx *ctx, int32_t trials, lbm_tile *best);
+
+/* Average device time of the fused step kernel over the steps launched
+ * since the last call, measured with HIP events on the context's stream
+ * when timing is enabled (lbm_set_timing(ctx, 1)).  Synchronises. */
+lbm_status lbm_set_timing(lbm_ctx *ctx, int32_t enable);
+lbm_status lbm_kernel_time(lbm_ctx *ctx, double *avg_ms, int64_t *launches);
+
+int64_t lbm_step_count(const lbm_ctx *ctx);
+const char *lbm_status_string(lbm_status s);
+const char *lbm_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Batched independent runs (periodic lattices, common op and storage): one
+ * persistent launch advances every run by one step; nsteps launches are
+ * captured once in a hipGraph and replayed.
+ * ------------------------------------------------------------------------- */
+lbm_status lbm_batch_workspace_bytes(const lbm_params *runs, int32_t n, size_t *bytes);
+lbm_status lbm_batch_create(const lbm_params *runs, int32_t n, void *dev_ws, size_t ws_bytes,
+                            void *hip_stream, lbm_batch **out);
+lbm_status lbm_batch_destroy(lbm_batch *b);
+lbm_status lbm_batch_init_droplets(lbm_batch *b, int32_t run, const lbm_droplet *d, int32_t n,
+                                   double rho_L, double rho_V, double W);
+lbm_status lbm_batch_init_fields(lbm_batch *b, int32_t run, const double *rho, const double *u);
+/* graph_steps > 0: capture that many steps in a hipGraph and replay it;
+ * 0: plain launches. */
+lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps, int32_t graph_steps);
+lbm_status lbm_batch_read_fields(lbm_batch *b, int32_t run, double *rho, double *u, double *p);
+lbm_status lbm_batch_read_populations(lbm_batch *b, int32_t run, double *f);
+/* Persistent grid size (blocks) and per-run tiles chosen by timing candidates;
+ * synchronises; state unchanged. */
+lbm_status lbm_batch_autotune(lbm_batch *b, int32_t trials, int32_t *best_blocks);
+lbm_status lbm_batch_set_blocks(lbm_batch *b, int32_t blocks);
+lbm_status lbm_batch_kernel_time(lbm_batch *b, double *avg_ms, int64_t *launches);
+int64_t lbm_batch_nodes(const lbm_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRT_LBM_H */

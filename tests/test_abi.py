@@ -1,0 +1,99 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+the header declares, and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1805_08643_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "mrt_lbm.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = binding.lib()
+    names = header_functions()
+    assert len(names) >= 30
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(binding.SIGNATURES) == names
+
+
+def test_params_default_and_workspace_size():
+    p = binding.lbm_params_default()
+    assert (p.nx, p.ny, p.nz) == (32, 32, 32) and p.G == -1.0 and p.eos_b == 4.0
+    n = binding.lbm_workspace_bytes(p)
+    N = 32 ** 3
+    pops = 19 * N * 4
+    assert n >= 2 * pops + N * 4
+    p.storage = binding.STORAGE["f16s"]
+    assert binding.lbm_workspace_bytes(p) < n
+    p.storage = binding.STORAGE["f64"]
+    assert binding.lbm_workspace_bytes(p) > n
+
+
+@pytest.mark.parametrize("field,value", [("nx", 0), ("s_nu", 2.0), ("s_e", 0.0), ("G", 0.5), ("op", 7),
+                                         ("storage", 9), ("T_over_Tc", -1.0), ("theta_wall_deg", 180.0),
+                                         ("reserved0", 1)])
+def test_invalid_params_rejected(field, value):
+    p = binding.lbm_params_default()
+    setattr(p, field, value)
+    n = ctypes.c_size_t(0)
+    st = binding.lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n))
+    assert st == -1
+    assert binding.lbm_last_error()
+
+
+def test_walls_need_two_planes():
+    p = binding.lbm_params_default()
+    p.wall_z, p.nz = 1, 1
+    n = ctypes.c_size_t(0)
+    assert binding.lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == -1
+
+
+def test_create_rejects_small_or_misaligned_workspace_without_gpu():
+    p = binding.lbm_params_default()
+    need = binding.lbm_workspace_bytes(p)
+    ctx = ctypes.c_void_p()
+    L = binding.lib()
+    st = L.lbm_create(ctypes.byref(p), ctypes.c_void_p(4096), need - 1, None, ctypes.byref(ctx))
+    assert st == -2 and not ctx.value
+    st = L.lbm_create(ctypes.byref(p), ctypes.c_void_p(4096 + 8), need, None, ctypes.byref(ctx))
+    assert st == -1
+    st = L.lbm_create(ctypes.byref(p), None, need, None, ctypes.byref(ctx))
+    assert st == -1
+
+
+def test_batch_validation():
+    a = binding.lbm_params_default()
+    b = binding.lbm_params_default()
+    b.op = binding.OP["orth"]
+    arr = (binding.LbmParams * 2)(a, b)
+    n = ctypes.c_size_t(0)
+    assert binding.lib().lbm_batch_workspace_bytes(arr, 2, ctypes.byref(n)) == -1
+    b.op = a.op
+    b.wall_z = 1
+    arr = (binding.LbmParams * 2)(a, b)
+    assert binding.lib().lbm_batch_workspace_bytes(arr, 2, ctypes.byref(n)) == -5
+    arr = (binding.LbmParams * 2)(a, a)
+    assert binding.lib().lbm_batch_workspace_bytes(arr, 2, ctypes.byref(n)) == 0
+    assert n.value >= 2 * binding.lbm_workspace_bytes(a)
+
+
+def test_status_strings():
+    assert binding.lbm_status_string(0) == "ok"
+    assert binding.lbm_status_string(-4) == "non-finite populations"
+
+
+def test_make_params_mapping():
+    p = binding.make_params(dict(nx=8, ny=9, nz=10, tau_nu=0.8, s_e=1.1, s_q=1.2, s_pi=1.4, op="orth",
+                                 storage="f16s", rho_ref=0.01, gravity=(0, 0, -1e-6), wall_z=1))
+    assert (p.nx, p.ny, p.nz, p.wall_z, p.op, p.storage) == (8, 9, 10, 1, 1, 2)
+    assert p.s_nu == 1.25 and p.s_eps == 1.4 and p.s_m == 1.2 and p.gravity[2] == -1e-6

@@ -1,0 +1,127 @@
+"""Batched runs: one persistent launch per step over many independent
+lattices of uneven size, plain and hipGraph-replayed, against the oracle and
+against single-lattice launches."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs as li
+from oracle import ref
+from paper_1805_08643_amd import binding
+from paper_1805_08643_amd.binding import Lattice
+
+pytestmark = pytest.mark.gpu
+
+
+class Batch:
+    def __init__(self, cfgs):
+        self.cfgs = cfgs
+        n = len(cfgs)
+        self.params = (binding.LbmParams * n)(*[binding.make_params(c) for c in cfgs])
+        nb = ctypes.c_size_t(0)
+        binding.check(binding.lib().lbm_batch_workspace_bytes(self.params, n, ctypes.byref(nb)),
+                      "lbm_batch_workspace_bytes")
+        self.ws = torch.empty(nb.value + 256, dtype=torch.uint8, device="cuda")
+        ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        h = ctypes.c_void_p()
+        st = torch.cuda.current_stream().cuda_stream
+        binding.check(binding.lib().lbm_batch_create(self.params, n, ctypes.c_void_p(ptr), nb.value,
+                                                     ctypes.c_void_p(st), ctypes.byref(h)), "lbm_batch_create")
+        self.h = h
+
+    def init_fields(self, k, rho, u):
+        r = torch.as_tensor(rho, device="cuda").contiguous()
+        v = torch.as_tensor(u, device="cuda").contiguous()
+        binding.check(binding.lib().lbm_batch_init_fields(self.h, k, ctypes.c_void_p(r.data_ptr()),
+                                                          ctypes.c_void_p(v.data_ptr())), "init")
+        torch.cuda.synchronize()
+
+    def step(self, n, graph_steps=0):
+        binding.check(binding.lib().lbm_batch_step(self.h, n, graph_steps), "lbm_batch_step")
+
+    def pops(self, k):
+        c = self.cfgs[k]
+        f = torch.empty((19, c["nx"] * c["ny"] * c["nz"]), dtype=torch.float64, device="cuda")
+        binding.check(binding.lib().lbm_batch_read_populations(self.h, k, ctypes.c_void_p(f.data_ptr())), "read")
+        return f.cpu().numpy()
+
+    def close(self):
+        binding.check(binding.lib().lbm_batch_destroy(self.h), "destroy")
+
+
+def _runs(storage, sizes=(12, 16, 20, 24, 18), seed=5):
+    rng = np.random.default_rng(seed)
+    out = []
+    for L in sizes:
+        t = float(rng.uniform(0.6, 0.9))
+        tau = float(rng.uniform(0.6, 1.2))
+        p = li.params(L, L, L, T_over_Tc=t, tau_nu=tau, storage=storage)
+        rl, rv = li.coexistence(t)
+        p["rho_ref"] = rv
+        init = dict(droplets=[dict(center=(L / 2, L / 2, L / 2), r0=0.25 * L)], rho_L=rl, rho_V=rv, W=2.0)
+        out.append((p, init))
+    return out
+
+
+@pytest.mark.parametrize("graph_steps", [0, 2, 3])
+def test_batch_fp64_matches_oracle(graph_steps):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    runs = _runs("f64")
+    print(f"[gpu] batch f64 runs={[r[0]['nx'] for r in runs]} graph_steps={graph_steps}", flush=True)
+    b = Batch([r[0] for r in runs])
+    fields = [li.init_fields(p, i) for p, i in runs]
+    for k, (rho, u) in enumerate(fields):
+        b.init_fields(k, rho, u)
+    b.step(6, graph_steps)
+    for k, (p, _) in enumerate(runs):
+        got = b.pops(k)
+        op = ref.make_params(p)
+        want = ref.step(op, ref.equilibrium(op, *fields[k]), 6)
+        e = float((np.abs(got - want) / want.sum(0)[None]).max())
+        print(f"  run {k} L={p['nx']}: err {e:.3e}")
+        assert e < 1e-12
+    b.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16s"])
+def test_batch_bit_identical_to_single_lattices(storage):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    runs = _runs(storage, sizes=(32, 48, 20, 36))
+    b = Batch([r[0] for r in runs])
+    for k, (p, init) in enumerate(runs):
+        b.init_fields(k, *li.init_fields(p, init))
+    b.step(5, 4)  # one 4-step graph replay + one plain launch
+    for k, (p, init) in enumerate(runs):
+        lat = Lattice(p)
+        lat.init_fields(*li.init_fields(p, init)).step(5)
+        assert np.array_equal(b.pops(k), lat.read_populations().cpu().numpy()), k
+        lat.close()
+    b.close()
+
+
+def test_batch_full_workload_sampled_runs():
+    """The 256-run workload (L in {32, 48, 64, 96}), FP32: eight runs checked
+    against the oracle after 3 steps."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    runs = li.c5_batch()
+    cfgs = [dict(p, storage="f32") for p, _ in runs]
+    b = Batch(cfgs)
+    for k, (p, init) in enumerate(runs):
+        lib_d = binding._droplet_array(init["droplets"])
+        binding.check(binding.lib().lbm_batch_init_droplets(b.h, k, lib_d, 1, init["rho_L"], init["rho_V"],
+                                                            init["W"]), "init_droplets")
+    b.step(3, 3)
+    for k in [0, 1, 7, 64, 100, 128, 200, 255]:
+        p, init = runs[k]
+        got = b.pops(k)
+        op = ref.make_params(p)
+        want = ref.step(op, ref.equilibrium(op, *li.init_fields(p, init)), 3)
+        e = float((np.abs(got - want) / want.sum(0)[None]).max())
+        print(f"  run {k} L={p['nx']}: err {e:.3e}")
+        assert e < 1.5e-5
+    b.close()

@@ -1,0 +1,317 @@
+"""GPU parity: the HIP library, called through the C ABI, against the FP64
+oracle on the same seeded inputs.
+
+Error measure: for populations, max over nodes x and directions a of
+|f_gpu - f_oracle| / rho_oracle(x) (density-normalised absolute error; a
+population is at most rho and near-zero populations have no meaningful
+relative error).  Tolerances:
+  * FP64 storage and arithmetic: 1e-12 (stated bound for FP64 runs).
+  * FP32: one step rounds every population once on store (2^-24 relative)
+    and the collision forms moment differences of O(rho) size, ~30 roundings
+    deep: ~30 * 6e-8 = 2e-6 per step; bound 5e-6 after one step, growing
+    linearly with the number of steps (5e-6 * steps).
+  * F16 shifted: each stored h = f - w rho_ref carries 2^-11 relative error,
+    h <= w |rho - rho_ref| <= |rho - rho_ref| / 3; the collision mixes ~19
+    such inputs with weights <= 1: bound 2^-11 * |rho - rho_ref| * 4 per step
+    plus the FP32 bound.
+"""
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs as li
+from oracle import ref
+from paper_1805_08643_amd import tuning
+from paper_1805_08643_amd.binding import Lattice
+
+pytestmark = pytest.mark.gpu
+
+Q = 19
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def gpu_states(cfg, rho, u, checkpoints, tile=None):
+    _need_gpu()
+    print(f"[gpu] {cfg['nx']}x{cfg['ny']}x{cfg['nz']} op={cfg.get('op')} storage={cfg.get('storage')} "
+          f"wall={cfg.get('wall_z', 0)} tile={tile} steps={checkpoints}", flush=True)
+    lat = Lattice(cfg)
+    if tile is not None:
+        lat.set_tile(*tile)
+    lat.init_fields(rho, u)
+    out, done = [], 0
+    for s in checkpoints:
+        lat.step(s - done)
+        done = s
+        out.append(lat.read_populations().cpu().numpy())
+    lat.close()
+    return out
+
+
+def oracle_states(cfg, rho, u, checkpoints):
+    p = ref.make_params(cfg)
+    f = ref.equilibrium(p, rho, u)
+    out, done = [], 0
+    for s in checkpoints:
+        f = ref.step(p, f, s - done)
+        done = s
+        out.append(f)
+    return out
+
+
+def rho_err(got, want):
+    rho = want.sum(0)
+    return float((np.abs(got - want) / rho[None, :]).max())
+
+
+CASES = {
+    # name: (cfg, init, tile)
+    "droplet_32": lambda op: (*li.c1_droplet(op=op), (32, 8, 8)),
+    "ragged_70x37x21": lambda op: (dict(li.c3_two_droplets(n=64, op=op)[0], nx=70, ny=37, nz=21),
+                                   dict(li.c3_two_droplets(n=64)[1]), (32, 8, 8)),
+    "walls_40x33x19_60deg": lambda op: (*li.c4_sessile(60.0, nx=40, ny=33, nz=19, r0=8.0), (16, 8, 7)),
+    "walls_37x20x12_120deg": lambda op: (*li.c4_sessile(120.0, nx=37, ny=20, nz=12, r0=6.0), (32, 4, 5)),
+}
+
+
+def _case(name, op, storage):
+    cfg, init, tile = CASES[name](op)
+    cfg = dict(cfg, op=op, storage=storage)
+    if storage == "f16s":
+        cfg["rho_ref"] = init["rho_V"]
+    if name.startswith("ragged"):
+        # droplets placed for a 64^3 box; shift into the ragged box
+        init = dict(init, droplets=[dict(d, center=(d["center"][0] + 3, d["center"][1] - 14, d["center"][2] - 22))
+                                    for d in init["droplets"]])
+    rho, u = li.init_fields(cfg, init)
+    return cfg, rho, u, tile
+
+
+@pytest.mark.parametrize("op", ["nonorth", "orth"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp64_parity(name, op):
+    cfg, rho, u, tile = _case(name, op, "f64")
+    cps = [0, 1, 5] if name != "droplet_32" else [0, 1, 10, 100]
+    got = gpu_states(cfg, rho, u, cps, tile)
+    want = oracle_states(cfg, rho, u, cps)
+    for s, g, w in zip(cps, got, want):
+        e = rho_err(g, w)
+        print(f"  step {s}: err {e:.3e}")
+        assert e < 1e-12, (s, e)
+
+
+def test_fp64_parity_500_steps_droplet_32():
+    """The 32^3 stationary droplet at steps 1, 10, 100, 500."""
+    cfg, rho, u, tile = _case("droplet_32", "nonorth", "f64")
+    cps = [1, 10, 100, 500]
+    got = gpu_states(cfg, rho, u, cps, tile)
+    want = oracle_states(cfg, rho, u, cps)
+    for s, g, w in zip(cps, got, want):
+        e = rho_err(g, w)
+        print(f"  step {s}: err {e:.3e}")
+        assert e < 1e-12, (s, e)
+
+
+@pytest.mark.parametrize("op", ["nonorth", "orth"])
+@pytest.mark.parametrize("name", ["droplet_32", "ragged_70x37x21", "walls_40x33x19_60deg"])
+def test_fp32_parity(name, op):
+    cfg, rho, u, tile = _case(name, op, "f32")
+    cps = [1, 10]
+    got = gpu_states(cfg, rho, u, cps, tile)
+    want = oracle_states(cfg, rho, u, cps)
+    for s, g, w in zip(cps, got, want):
+        e = rho_err(g, w)
+        print(f"  step {s}: err {e:.3e} (bound {5e-6 * s:.1e})")
+        assert e < 5e-6 * s, (s, e)
+
+
+@pytest.mark.parametrize("name", ["droplet_32", "ragged_70x37x21", "walls_40x33x19_60deg"])
+def test_f16s_parity(name):
+    cfg, rho, u, tile = _case(name, "nonorth", "f16s")
+    cps = [1, 10]
+    got = gpu_states(cfg, rho, u, cps, tile)
+    want = oracle_states(cfg, rho, u, cps)
+    rr = cfg["rho_ref"]
+    for s, g, w in zip(cps, got, want):
+        r = w.sum(0)
+        bound = s * (4 * 2.0 ** -11 * np.abs(r - rr) + 5e-6 * r)
+        e = np.abs(g - w).max(0)
+        print(f"  step {s}: max err/bound {float((e / bound).max()):.3f}, err/rho {rho_err(g, w):.3e}")
+        assert np.all(e <= bound), s
+
+
+def test_tiles_give_bit_identical_results():
+    """Every node's arithmetic is independent of the tiling, so any tile
+    shape (including ragged tails) must give the same bits."""
+    cfg, rho, u, _ = _case("ragged_70x37x21", "nonorth", "f32")
+    ref_state = None
+    for tile in [(32, 8, 8), (64, 4, 21), (16, 16, 3), (70, 4, 5), (8, 32, 1)]:
+        s = gpu_states(cfg, rho, u, [3], tile)[0]
+        if ref_state is None:
+            ref_state = s
+        else:
+            assert np.array_equal(s, ref_state), tile
+
+
+def test_init_droplets_on_device_matches_generator():
+    _need_gpu()
+    cfg, init = li.c3_two_droplets(n=48)
+    cfg = dict(cfg, storage="f64")
+    rho, u = li.init_fields(cfg, init)
+    lat = Lattice(cfg)
+    lat.init_droplets(init["droplets"], init["rho_L"], init["rho_V"], init["W"])
+    got = lat.read_populations().cpu().numpy()
+    lat.close()
+    want = ref.equilibrium(ref.make_params(cfg), rho, u)
+    assert rho_err(got, want) < 1e-13
+
+
+def test_read_fields_and_diagnostics_match_oracle():
+    cfg, rho, u, tile = _case("walls_40x33x19_60deg", "nonorth", "f64")
+    _need_gpu()
+    lat = Lattice(cfg)
+    lat.set_tile(*tile)
+    lat.init_fields(rho, u).step(4)
+    fl = {k: v.cpu().numpy() for k, v in lat.read_fields().items()}
+    c = (20.0, 16.5, 8.0)
+    d = lat.diagnostics(center=c, r_in=4.0, r_out=12.0)
+    lat.close()
+    p = ref.make_params(cfg)
+    f = ref.step(p, ref.equilibrium(p, rho, u), 4)
+    o = ref.fields(p, f)
+    for k in ("rho", "p"):
+        assert np.abs(fl[k] - o[k]).max() < 1e-12 * np.abs(o[k]).max(), k
+    assert np.abs(fl["u"] - o["u"]).max() < 1e-12
+    assert abs(d["mass"] - o["rho"].sum()) < 1e-12 * o["rho"].sum()
+    mom = (np.array(ref.moments.VELOCITIES).T.astype(float) @ f).sum(1) + 0.5 * o["F"].sum(1)
+    assert np.allclose(d["momentum"], mom, rtol=1e-10, atol=1e-13)
+    assert abs(d["max_u"] - np.sqrt((o["u"] ** 2).sum(0)).max()) < 1e-12
+    nx, ny, nz = cfg["nx"], cfg["ny"], cfg["nz"]
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    dx = np.remainder(x - c[0] + nx / 2, nx) - nx / 2
+    dy = np.remainder(y - c[1] + ny / 2, ny) - ny / 2
+    dz = z - c[2]
+    r2 = (dx * dx + dy * dy + dz * dz).ravel()
+    inside, outside = r2 < 16.0, r2 > 144.0
+    assert d["n_in"] == inside.sum() and d["n_out"] == outside.sum()
+    assert abs(d["p_in"] - o["p"][inside].sum()) < 1e-12 * abs(o["p"][inside].sum())
+    assert abs(d["rho_out"] - o["rho"][outside].sum()) < 1e-12 * o["rho"][outside].sum()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_mass_conservation(storage):
+    _need_gpu()
+    cfg, init = li.c3_two_droplets(n=64)
+    cfg = dict(cfg, storage=storage)
+    lat = Lattice(cfg)
+    lat.init_droplets(init["droplets"], init["rho_L"], init["rho_V"], init["W"])
+    m0 = lat.diagnostics()["mass"]
+    lat.step(200)
+    d = lat.diagnostics()
+    lat.close()
+    tol = 1e-13 if storage == "f64" else 1e-6
+    print(f"  {storage}: |dM|/M = {abs(d['mass'] - m0) / m0:.3e}")
+    assert abs(d["mass"] - m0) / m0 < tol
+    assert d["status"] == 0 and d["nonfinite"] == 0
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16s"])
+def test_save_load_resume_is_bit_identical(storage):
+    _need_gpu()
+    cfg, init = li.c1_droplet()
+    cfg = dict(cfg, storage=storage, rho_ref=init["rho_V"])
+    a = Lattice(cfg)
+    a.init_droplets(init["droplets"], init["rho_L"], init["rho_V"], init["W"]).step(7)
+    buf = a.save_state()
+    a.step(7)
+    fa = a.read_populations().cpu().numpy()
+    b = Lattice(cfg)
+    b.load_state(buf)
+    assert b.steps == 7
+    b.step(7)
+    fb = b.read_populations().cpu().numpy()
+    assert np.array_equal(fa, fb)
+    a.close()
+    b.close()
+
+
+def test_autotune_leaves_state_unchanged():
+    _need_gpu()
+    cfg, init = li.c1_droplet()
+    cfg = dict(cfg, storage="f32")
+    lat = Lattice(cfg)
+    lat.init_droplets(init["droplets"], init["rho_L"], init["rho_V"], init["W"]).step(2)
+    f0 = lat.read_populations().cpu().numpy()
+    t = lat.autotune(trials=1)
+    assert lat.get_tile() == t
+    f1 = lat.read_populations().cpu().numpy()
+    assert np.array_equal(f0, f1)
+    lat.step(1)
+    lat.close()
+
+
+def test_nonfinite_detected():
+    _need_gpu()
+    cfg, init = li.c1_droplet(n=16, r0=4.0)
+    cfg = dict(cfg, nx=16, ny=16, nz=16, storage="f32")
+    lat = Lattice(cfg)
+    rho, u = li.init_fields(cfg, init)
+    f = ref.equilibrium(ref.make_params(cfg), rho, u)
+    f[3, 100] = np.nan
+    lat.write_populations(f)
+    d = lat.diagnostics()
+    assert d["status"] == -4 and d["nonfinite"] >= 1
+    lat.close()
+
+
+# ---------------------------------------------------------------------------
+# Full-size workloads in their benchmark launch shape: one step from the
+# initial condition, compared at sampled nodes computed one by one.
+# ---------------------------------------------------------------------------
+FULL = {
+    "laplace_128": lambda: li.c2_laplace(20),
+    "two_droplets_256": lambda: li.c3_two_droplets(),
+    "sessile_384x384x192": lambda: li.c4_sessile(60.0),
+}
+
+
+@pytest.mark.parametrize("workload,storage", [("laplace_128", "f64"), ("laplace_128", "f32"),
+                                              ("two_droplets_256", "f32"), ("two_droplets_256", "f16s"),
+                                              ("sessile_384x384x192", "f32")])
+def test_full_size_sampled_parity(workload, storage):
+    _need_gpu()
+    cfg, init = FULL[workload]()
+    cfg = dict(cfg, storage=storage, rho_ref=init["rho_V"])
+    rho, u = li.init_fields(cfg, init)
+    N = rho.size
+    rng = np.random.default_rng(2024)
+    idx = np.unique(np.concatenate([rng.integers(0, N, 3000),
+                                    np.flatnonzero(np.abs(rho - 0.5 * (init["rho_L"] + init["rho_V"]))
+                                                   < 0.25 * (init["rho_L"] - init["rho_V"]))[::97][:2000],
+                                    [0, N - 1]]))
+    tile = tuning.tile_for(workload, storage)
+    print(f"[gpu] {workload} {storage} tile={tile} samples={idx.size}", flush=True)
+    lat = Lattice(cfg)
+    if tile:
+        lat.set_tile(*tile)
+    lat.init_fields(rho, u).step(1)
+    f = lat.read_populations()
+    got = f[:, torch.as_tensor(idx, device=f.device)].cpu().numpy().T
+    lat.close()
+    del f
+    p = ref.make_params(cfg)
+    f0 = ref.equilibrium(p, rho, u)
+    want = ref.step_sampled(p, f0, idx)
+    r = want.sum(1)
+    err = np.abs(got - want)
+    if storage == "f64":
+        bound = 1e-12 * r[:, None]
+    elif storage == "f32":
+        bound = 5e-6 * r[:, None]
+    else:
+        bound = 4 * 2.0 ** -11 * np.abs(r - cfg["rho_ref"])[:, None] + 5e-6 * r[:, None]
+    print(f"  max err/rho {float((err / r[:, None]).max()):.3e}")
+    assert np.all(err <= bound)
