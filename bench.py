@@ -41,9 +41,9 @@ def parse():
 def make_lattice(storage, op):
     import lbm_inputs as li
     from paper_1805_08643_amd import tuning
-    from paper_1805_08643_amd.binding import Lattice
+    from paper_1805_08643_amd.binding import Lattice, f16_exp_for
     cfg, init = li.c3_two_droplets(op=op)
-    cfg = dict(cfg, storage=storage, rho_ref=init["rho_V"])
+    cfg = dict(cfg, storage=storage, rho_ref=init["rho_V"], f16_exp=f16_exp_for(1.25 * init["rho_L"]))
     lat = Lattice(cfg, "cuda:0")
     tile = tuning.tile_for(WORKLOAD, storage)
     if tile:

@@ -56,8 +56,10 @@ enum { LBM_OP_NONORTH = 0, /* Eqs. (7)-(14), (16): the paper's model */
        LBM_OP_ORTH = 1     /* Gram-Schmidt orthogonal D3Q19 basis (comparison) */ };
 
 /* Population storage in HBM.  Arithmetic is FP64 for F64 storage and FP32
- * otherwise.  F16S stores h_a = fbar*_a - w_a rho_ref in IEEE binary16
- * (round to nearest even) with w = 1/3, 1/18, 1/36 by velocity class. */
+ * otherwise.  F16S stores h_a = (fbar*_a - w_a rho_ref) * 2^f16_exp in IEEE
+ * binary16 (round to nearest even) with w = 1/3, 1/18, 1/36 by velocity
+ * class; the power-of-two factor is exact and only moves h into the normal
+ * range of binary16. */
 enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16S = 2 };
 
 /* Pseudopotential form (text after Eq. (15)). */
@@ -71,7 +73,9 @@ typedef struct lbm_params {
     int32_t op;             /* LBM_OP_* */
     int32_t storage;        /* LBM_STORE_* */
     int32_t psi_form;       /* LBM_PSI_* */
-    int32_t reserved0;      /* must be 0 */
+    int32_t f16_exp;        /* F16S: stored value is (fbar - w rho_ref) * 2^f16_exp,
+                               in [-24, 24]; pick it so the largest |fbar - w rho_ref|
+                               scaled stays below 2^15 (ignored otherwise) */
     double rho_ref;         /* F16S shift density (ignored otherwise) */
     /* Relaxation rates, Eq. (11); each in (0, 2).  ORTH also uses s_eps (energy
      * square) and s_m (cubic m_x,y,z rows). */

@@ -148,9 +148,20 @@ def c4_sessile(theta_deg=60.0, nx=384, ny=384, nz=192, r0=40.0):
     return p, init
 
 
+def interface_recipe(T_over_Tc):
+    """EOS constant a and initial interface width W for a reduced temperature:
+    linear between the paper's T = 0.6 T_c setting (a = 0.25, W = 5, about
+    five lattice units of interface) and a = 0.5, W = 2 at T = 0.9 T_c.  With
+    a = 0.5 and W = 2 a droplet at T = 0.6 T_c diverges within a few steps
+    (checked with the oracle)."""
+    s = (float(T_over_Tc) - 0.6) / 0.3
+    return 0.25 + 0.25 * s, 5.0 - 3.0 * s
+
+
 def c5_batch(n_runs=256, seed=1805, sizes=(32, 48, 64, 96)):
     """Independent periodic droplet runs: L ~ U{sizes}, r0 = L/4 + U[-2, 2],
-    T/Tc ~ U[0.6, 0.9], tau_nu ~ U[0.6, 1.2]; drawn per run in that order."""
+    T/Tc ~ U[0.6, 0.9], tau_nu ~ U[0.6, 1.2]; drawn per run in that order.
+    a and W follow ``interface_recipe``."""
     rng = np.random.default_rng(seed)
     runs = []
     for _ in range(n_runs):
@@ -158,10 +169,11 @@ def c5_batch(n_runs=256, seed=1805, sizes=(32, 48, 64, 96)):
         dr = float(rng.uniform(-2.0, 2.0))
         t = float(rng.uniform(0.6, 0.9))
         tau = float(rng.uniform(0.6, 1.2))
-        p = params(L, L, L, T_over_Tc=t, tau_nu=tau)
+        a, W = interface_recipe(t)
+        p = params(L, L, L, T_over_Tc=t, tau_nu=tau, eos_a=a)
         rl, rv = coexistence(t)
         init = dict(droplets=[dict(center=(L / 2, L / 2, L / 2), r0=0.25 * L + dr)],
-                    rho_L=rl, rho_V=rv, W=2.0)
+                    rho_L=rl, rho_V=rv, W=W)
         runs.append((p, init))
     return runs
 

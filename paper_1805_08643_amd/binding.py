@@ -28,7 +28,7 @@ class LbmParams(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
         ("wall_z", ctypes.c_int32), ("op", ctypes.c_int32), ("storage", ctypes.c_int32),
-        ("psi_form", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("psi_form", ctypes.c_int32), ("f16_exp", ctypes.c_int32),
         ("rho_ref", ctypes.c_double),
         ("s_e", ctypes.c_double), ("s_nu", ctypes.c_double), ("s_q", ctypes.c_double),
         ("s_pi", ctypes.c_double), ("s_eps", ctypes.c_double), ("s_m", ctypes.c_double),
@@ -272,6 +272,7 @@ def make_params(cfg: dict) -> LbmParams:
     p.storage = STORAGE[cfg.get("storage", "f32")]
     p.psi_form = PSI[cfg.get("psi_form", "sqrt_cs")]
     p.rho_ref = float(cfg.get("rho_ref", 0.0))
+    p.f16_exp = int(cfg.get("f16_exp", 0))
     s_nu = 1.0 / cfg["tau_nu"] if "tau_nu" in cfg else cfg.get("s_nu", 1.0)
     if "rates_all" in cfg:
         s = float(cfg["rates_all"])
@@ -414,6 +415,13 @@ class Lattice:
     @property
     def steps(self):
         return lbm_step_count(self.ctx)
+
+
+def f16_exp_for(rho_max: float) -> int:
+    """Exponent offset for shifted binary16 storage: the largest shifted
+    population (at most the rest population rho_max / 3) scaled by 2^e stays
+    below 2^15, so nothing overflows and small shifted values stay normal."""
+    return int(math.floor(math.log2(2.0 ** 15 / (rho_max / 3.0))))
 
 
 def storage_bytes(storage: str) -> int:

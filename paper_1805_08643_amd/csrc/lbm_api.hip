@@ -61,7 +61,7 @@ lbm_status validate(const lbm_params *p) {
         return fail(LBM_ERR_INVALID_ARG, "unknown storage %d", p->storage);
     if (p->psi_form != LBM_PSI_SQRT_CS && p->psi_form != LBM_PSI_EXP)
         return fail(LBM_ERR_INVALID_ARG, "unknown psi_form %d", p->psi_form);
-    if (p->reserved0 != 0) return fail(LBM_ERR_INVALID_ARG, "reserved0 must be 0");
+    if (p->f16_exp < -24 || p->f16_exp > 24) return fail(LBM_ERR_INVALID_ARG, "f16_exp %d outside [-24, 24]", p->f16_exp);
     const double rates[6] = {p->s_e, p->s_nu, p->s_q, p->s_pi, p->s_eps, p->s_m};
     const char *names[6] = {"s_e", "s_nu", "s_q", "s_pi", "s_eps", "s_m"};
     for (int k = 0; k < 6; ++k)
@@ -112,6 +112,7 @@ PhysD make_phys(const lbm_params &p) {
     d.tan_wall = std::tan((90.0 - p.theta_wall_deg) * M_PI / 180.0);
     d.ghost_rho_min = p.ghost_rho_min;
     d.rho_ref = p.storage == LBM_STORE_F16S ? p.rho_ref : 0.0;
+    d.h_exp = p.storage == LBM_STORE_F16S ? p.f16_exp : 0;
     d.psi_form = p.psi_form;
     return d;
 }

@@ -40,34 +40,6 @@ enum { ST_F64 = 0, ST_F32 = 1, ST_F16S = 2 };
 enum { PSI_SQRT_CS = 0, PSI_EXP = 1 };
 
 // ---------------------------------------------------------------------------
-// Storage traits.  T = element type in HBM, R = arithmetic type.
-// ---------------------------------------------------------------------------
-template <int S> struct Storage;
-template <> struct Storage<ST_F64> {
-    using T = double;
-    using R = double;
-    __device__ static inline R load(const T *p, R) { return __builtin_nontemporal_load(p); }
-    __device__ static inline void store(T *p, R v, R) { __builtin_nontemporal_store(v, p); }
-};
-template <> struct Storage<ST_F32> {
-    using T = float;
-    using R = float;
-    __device__ static inline R load(const T *p, R) { return __builtin_nontemporal_load(p); }
-    __device__ static inline void store(T *p, R v, R) { __builtin_nontemporal_store(v, p); }
-};
-template <> struct Storage<ST_F16S> {
-    using T = uint16_t;  // IEEE binary16 bits of h = fbar - w rho_ref
-    using R = float;
-    __device__ static inline R load(const T *p, R shift) {
-        uint16_t bits = __builtin_nontemporal_load(p);
-        return __half2float(__ushort_as_half(bits)) + shift;
-    }
-    __device__ static inline void store(T *p, R v, R shift) {
-        __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v - shift)), p);
-    }
-};
-
-// ---------------------------------------------------------------------------
 // Physical constants in the arithmetic precision.
 // ---------------------------------------------------------------------------
 struct PhysD {  // host-filled, double
@@ -77,7 +49,7 @@ struct PhysD {  // host-filled, double
     double g[3];
     double tan_wall, ghost_rho_min, rho_ref;
     int psi_form;
-    int pad;
+    int h_exp;  // F16S exponent offset: stored h = (fbar - w rho_ref) * 2^h_exp
 };
 
 template <class R> struct Phys {
@@ -87,6 +59,7 @@ template <class R> struct Phys {
     R gx, gy, gz;
     R tan_wall, ghost_rho_min;
     R shift[3];          // w_class * rho_ref
+    R hs, hsi;           // 2^h_exp and 2^-h_exp (exact powers of two)
     int psi_form;
     __device__ inline void load(const PhysD &d) {
         G = (R)d.G;
@@ -113,9 +86,41 @@ template <class R> struct Phys {
         shift[0] = (R)(d.rho_ref / 3.0);
         shift[1] = (R)(d.rho_ref / 18.0);
         shift[2] = (R)(d.rho_ref / 36.0);
+        hs = (R)ldexp(1.0, d.h_exp);
+        hsi = (R)ldexp(1.0, -d.h_exp);
         psi_form = d.psi_form;
     }
     __device__ inline R sh(int a_) const { return a_ == 0 ? shift[0] : (a_ <= 6 ? shift[1] : shift[2]); }
+};
+
+// ---------------------------------------------------------------------------
+// Storage traits.  T = element type in HBM, R = arithmetic type.
+// ---------------------------------------------------------------------------
+template <int S> struct Storage;
+template <> struct Storage<ST_F64> {
+    using T = double;
+    using R = double;
+    __device__ static inline R load(const T *p, R, R) { return __builtin_nontemporal_load(p); }
+    __device__ static inline void store(T *p, R v, R, R) { __builtin_nontemporal_store(v, p); }
+};
+template <> struct Storage<ST_F32> {
+    using T = float;
+    using R = float;
+    __device__ static inline R load(const T *p, R, R) { return __builtin_nontemporal_load(p); }
+    __device__ static inline void store(T *p, R v, R, R) { __builtin_nontemporal_store(v, p); }
+};
+// binary16 bits of h = (fbar - w rho_ref) * 2^e.  load(p, shift, 2^-e),
+// store(p, v, shift, 2^e); the power-of-two factors are exact.
+template <> struct Storage<ST_F16S> {
+    using T = uint16_t;
+    using R = float;
+    __device__ static inline R load(const T *p, R shift, R hsi) {
+        uint16_t bits = __builtin_nontemporal_load(p);
+        return __half2float(__ushort_as_half(bits)) * hsi + shift;
+    }
+    __device__ static inline void store(T *p, R v, R shift, R hs) {
+        __builtin_nontemporal_store(__half_as_ushort(__float2half_rn((v - shift) * hs)), p);
+    }
 };
 
 // Precision-explicit math (no silent promotion of float to double).

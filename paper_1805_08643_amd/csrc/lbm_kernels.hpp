@@ -69,7 +69,7 @@ __device__ inline void pull(const typename Storage<S>::T *__restrict__ A, size_t
     const uint32_t r_q = (pq + y) * rowb, r_qm = (pq + ym) * rowb, r_qp = (pq + yp) * rowb;
     const uint32_t bx = (uint32_t)x * E, bxm = (uint32_t)xm * E, bxp = (uint32_t)xp * E;
     const uint32_t own = r_c + bx;
-#define LBM_LD(d, boff) ST::load(at(A + (size_t)(d) * N, (boff)), P.sh(d))
+#define LBM_LD(d, boff) ST::load(at(A + (size_t)(d) * N, (boff)), P.sh(d), P.hsi)
     f[0] = LBM_LD(0, own);
     f[1] = LBM_LD(1, r_c + bxm);
     f[2] = LBM_LD(2, r_c + bxp);
@@ -223,7 +223,7 @@ __device__ inline void tile_march(const typename Storage<S>::T *__restrict__ A,
             collide<R, OP>(fc, rc, Fx, Fy, Fz, acc2, P);
             const uint32_t own = (((uint32_t)z * ny + gy) * nx + gx) * (uint32_t)sizeof(typename ST::T);
 #pragma unroll
-            for (int a = 0; a < Q; ++a) ST::store(at(B + (size_t)a * N, own), fc[a], P.sh(a));
+            for (int a = 0; a < Q; ++a) ST::store(at(B + (size_t)a * N, own), fc[a], P.sh(a), P.hs);
         }
 #pragma unroll
         for (int a = 0; a < Q; ++a) fc[a] = fn[a];
@@ -476,7 +476,7 @@ __device__ inline void scatter_node(typename Storage<S>::T *__restrict__ A, cons
             sz = wrapi(sz, g.nz);
             idx = ((size_t)sz * g.ny + wrapi(y - ey(a), g.ny)) * g.nx + wrapi(x - ex(a), g.nx);
         }
-        ST::store(A + (size_t)d * g.N + idx, v[a], P.sh(a));
+        ST::store(A + (size_t)d * g.N + idx, v[a], P.sh(a), P.hs);
     }
 }
 

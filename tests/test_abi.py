@@ -41,7 +41,7 @@ def test_params_default_and_workspace_size():
 
 @pytest.mark.parametrize("field,value", [("nx", 0), ("s_nu", 2.0), ("s_e", 0.0), ("G", 0.5), ("op", 7),
                                          ("storage", 9), ("T_over_Tc", -1.0), ("theta_wall_deg", 180.0),
-                                         ("reserved0", 1)])
+                                         ("f16_exp", 30)])
 def test_invalid_params_rejected(field, value):
     p = binding.lbm_params_default()
     setattr(p, field, value)

@@ -57,10 +57,12 @@ def _runs(storage, sizes=(12, 16, 20, 24, 18), seed=5):
     for L in sizes:
         t = float(rng.uniform(0.6, 0.9))
         tau = float(rng.uniform(0.6, 1.2))
-        p = li.params(L, L, L, T_over_Tc=t, tau_nu=tau, storage=storage)
+        a, W = li.interface_recipe(t)
+        p = li.params(L, L, L, T_over_Tc=t, tau_nu=tau, storage=storage, eos_a=a)
         rl, rv = li.coexistence(t)
         p["rho_ref"] = rv
-        init = dict(droplets=[dict(center=(L / 2, L / 2, L / 2), r0=0.25 * L)], rho_L=rl, rho_V=rv, W=2.0)
+        p["f16_exp"] = binding.f16_exp_for(1.25 * rl)
+        init = dict(droplets=[dict(center=(L / 2, L / 2, L / 2), r0=0.25 * L)], rho_L=rl, rho_V=rv, W=W)
         out.append((p, init))
     return out
 
