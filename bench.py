@@ -35,7 +35,29 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy 5 times (HBM counter calibration)")
     return ap.parse_args()
+
+
+def copy_probe():
+    """A plain device-to-device copy of known size: 1 GiB read + 1 GiB written
+    per launch, used to scale the HBM byte counters of rocprofv3."""
+    import torch
+    n = 1 << 28  # float32 elements = 1 GiB
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
+                      "ms_per_copy": round(ms, 4), "GBps_read_plus_write": round(8 * n / (ms * 1e-3) / 1e9, 1)}),
+          flush=True)
 
 
 def make_lattice(storage, op):
@@ -123,6 +145,9 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(2)
+    if a.copy_probe:
+        copy_probe()
+        return
     from paper_1805_08643_amd.binding import algorithmic_bytes_per_node
 
     lat, cfg, init = make_lattice(a.storage, a.op)

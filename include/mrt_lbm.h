@@ -57,9 +57,10 @@ enum { LBM_OP_NONORTH = 0, /* Eqs. (7)-(14), (16): the paper's model */
 
 /* Population storage in HBM.  Arithmetic is FP64 for F64 storage and FP32
  * otherwise.  F16S stores h_a = (fbar*_a - w_a rho_ref) * 2^f16_exp in IEEE
- * binary16 (round to nearest even) with w = 1/3, 1/18, 1/36 by velocity
- * class; the power-of-two factor is exact and only moves h into the normal
- * range of binary16. */
+ * binary16 with w = 1/3, 1/18, 1/36 by velocity class: the expression is
+ * evaluated exactly from the FP32 population and rounded once to nearest
+ * even; loading gives h_a 2^-f16_exp + w_a rho_ref rounded once to FP32.  The
+ * power-of-two factor only moves h into the normal range of binary16. */
 enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16S = 2 };
 
 /* Pseudopotential form (text after Eq. (15)). */

@@ -83,12 +83,13 @@ lbm_status validate(const lbm_params *p) {
         return fail(LBM_ERR_INVALID_ARG, "theta_wall_deg must be in (0, 180)");
     if (!std::isfinite(p->rho_ref) || !std::isfinite(p->ghost_rho_min))
         return fail(LBM_ERR_INVALID_ARG, "rho_ref / ghost_rho_min not finite");
-    // Kernels address one direction plane with 32-bit byte offsets.
+    // Kernels address five direction planes through one buffer descriptor
+    // with 32-bit offsets.
     const unsigned long long plane_bytes = (unsigned long long)p->nx * p->ny * p->nz *
                                            (p->storage == LBM_STORE_F64 ? 8 : (p->storage == LBM_STORE_F32 ? 4 : 2));
-    if (plane_bytes >= (1ULL << 32))
-        return fail(LBM_ERR_UNSUPPORTED, "lattice too large: one population plane is %llu bytes (limit 4 GiB)",
-                    plane_bytes);
+    if (5 * plane_bytes >= (1ULL << 32))
+        return fail(LBM_ERR_UNSUPPORTED,
+                    "lattice too large: five population planes take %llu bytes (limit 4 GiB)", 5 * plane_bytes);
     return LBM_OK;
 }
 

@@ -60,6 +60,7 @@ template <class R> struct Phys {
     R tan_wall, ghost_rho_min;
     R shift[3];          // w_class * rho_ref
     R hs, hsi;           // 2^h_exp and 2^-h_exp (exact powers of two)
+    R shs[3];            // shift * 2^h_exp
     int psi_form;
     __device__ inline void load(const PhysD &d) {
         G = (R)d.G;
@@ -88,56 +89,103 @@ template <class R> struct Phys {
         shift[2] = (R)(d.rho_ref / 36.0);
         hs = (R)ldexp(1.0, d.h_exp);
         hsi = (R)ldexp(1.0, -d.h_exp);
+        shs[0] = shift[0] * hs;
+        shs[1] = shift[1] * hs;
+        shs[2] = shift[2] * hs;
         psi_form = d.psi_form;
     }
     __device__ inline R sh(int a_) const { return a_ == 0 ? shift[0] : (a_ <= 6 ? shift[1] : shift[2]); }
+    __device__ inline R shh(int a_) const { return a_ == 0 ? shs[0] : (a_ <= 6 ? shs[1] : shs[2]); }
 };
 
 // ---------------------------------------------------------------------------
 // Storage traits.  T = element type in HBM, R = arithmetic type.
 // ---------------------------------------------------------------------------
 template <int S> struct Storage;
+
+// Raw buffer access: descriptor over one direction plane (base, size in
+// bytes), 32-bit per-lane offset, wave-uniform scalar offset.  The hardware
+// range check against the plane size makes every access bounds-checked.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int kBufWord3 = 0x00020000;  // dword 3 of a raw buffer descriptor on gfx9-family parts
+#ifndef LBM_BUF_AUX
+// Cache policy bits of the buffer accesses: 0 (default) keeps lines in L2 so
+// that the halo re-reads of neighbouring tiles hit; 2 marks them
+// non-temporal (measured slower on MI355X).
+#define LBM_BUF_AUX 0
+#endif
+__device__ inline rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, kBufWord3);
+}
+
 template <> struct Storage<ST_F64> {
     using T = double;
     using R = double;
     __device__ static inline R load(const T *p, R, R) { return __builtin_nontemporal_load(p); }
     __device__ static inline void store(T *p, R v, R, R) { __builtin_nontemporal_store(v, p); }
+    __device__ static inline R ldb(rsrc_t r, uint32_t vo, uint32_t so, R, R) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, LBM_BUF_AUX));
+    }
+    __device__ static inline void stb(R v, rsrc_t r, uint32_t vo, uint32_t so, R, R) {
+        using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, (int)vo, (int)so, LBM_BUF_AUX);
+    }
 };
 template <> struct Storage<ST_F32> {
     using T = float;
     using R = float;
     __device__ static inline R load(const T *p, R, R) { return __builtin_nontemporal_load(p); }
     __device__ static inline void store(T *p, R v, R, R) { __builtin_nontemporal_store(v, p); }
+    __device__ static inline R ldb(rsrc_t r, uint32_t vo, uint32_t so, R, R) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, LBM_BUF_AUX));
+    }
+    __device__ static inline void stb(R v, rsrc_t r, uint32_t vo, uint32_t so, R, R) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)vo, (int)so, LBM_BUF_AUX);
+    }
 };
-// binary16 bits of h = (fbar - w rho_ref) * 2^e.  load(p, shift, 2^-e),
-// store(p, v, shift, 2^e); the power-of-two factors are exact.
+// binary16 bits of h = (fbar - w rho_ref) * 2^e.  Loads return
+// h 2^-e + shift; stores round v 2^e - shift 2^e, a single fused
+// multiply-add whose exact result is rounded once to binary16 (the
+// power-of-two factors are exact, so it is (v - shift) 2^e rounded once).
 template <> struct Storage<ST_F16S> {
     using T = uint16_t;
     using R = float;
     __device__ static inline R load(const T *p, R shift, R hsi) {
         uint16_t bits = __builtin_nontemporal_load(p);
-        return __half2float(__ushort_as_half(bits)) * hsi + shift;
+        return fmaf(__half2float(__ushort_as_half(bits)), hsi, shift);
     }
-    __device__ static inline void store(T *p, R v, R shift, R hs) {
-        __builtin_nontemporal_store(__half_as_ushort(__float2half_rn((v - shift) * hs)), p);
+    __device__ static inline void store(T *p, R v, R shs, R hs) {
+        __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(fmaf(v, hs, -shs))), p);
+    }
+    __device__ static inline R ldb(rsrc_t r, uint32_t vo, uint32_t so, R shift, R hsi) {
+        const uint16_t bits = __builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, LBM_BUF_AUX);
+        return fmaf(__half2float(__ushort_as_half(bits)), hsi, shift);
+    }
+    __device__ static inline void stb(R v, rsrc_t r, uint32_t vo, uint32_t so, R shs, R hs) {
+        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(fmaf(v, hs, -shs))), r, (int)vo,
+                                              (int)so, LBM_BUF_AUX);
     }
 };
 
-// Precision-explicit math (no silent promotion of float to double).
-__device__ inline float r_sqrt(float v) { return sqrtf(v); }
+// Precision-explicit math (no silent promotion of float to double).  The
+// FP32 path uses the hardware reciprocal and square root (about 1 ulp); the
+// FP64 path keeps correctly rounded division and square root.
+__device__ inline float r_sqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
 __device__ inline double r_sqrt(double v) { return ::sqrt(v); }
 __device__ inline float r_exp(float v) { return expf(v); }
 __device__ inline double r_exp(double v) { return ::exp(v); }
+__device__ inline float r_rcp(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ inline double r_rcp(double v) { return 1.0 / v; }
 
 // Pseudopotential.  Square-root form: psi^2 = 2 (p_EOS - rho/3) / G with the
 // Carnahan-Starling p_EOS = rho R T (1 + n + n^2 - n^3) / (1 - n)^3 - a rho^2,
 // n = b rho / 4 (Eq. (58)).  Exponential form psi0 exp(-rho0 / rho).
 template <class R> __device__ inline R pseudo_psi(const Phys<R> &P, R rho) {
-    if (P.psi_form == PSI_EXP) return P.psi0 * r_exp(-P.rho0 / rho);
+    if (P.psi_form == PSI_EXP) return P.psi0 * r_exp(-P.rho0 * r_rcp(rho));
     R n = P.b4 * rho;
     R om = (R)1 - n;
     R num = (R)1 + n * ((R)1 + n * ((R)1 - n));
-    R peos = rho * P.RT * num / (om * om * om) - P.a * rho * rho;
+    R peos = rho * P.RT * num * r_rcp(om * om * om) - P.a * rho * rho;
     return r_sqrt(P.two_over_G * (peos - rho * (R)(1.0 / 3.0)));
 }
 
@@ -293,7 +341,7 @@ __device__ inline void collide(R f[Q], R rho, R Fx, R Fy, R Fz, R acc2, const Ph
                                R *uout = nullptr) {
     Pre<R> pr;
     pr.build(f);
-    const R inv_rho = (R)1 / rho;
+    const R inv_rho = r_rcp(rho);
     const R ux = (pr.jx() + (R)0.5 * Fx) * inv_rho;
     const R uy = (pr.jy() + (R)0.5 * Fy) * inv_rho;
     const R uz = (pr.jz() + (R)0.5 * Fz) * inv_rho;

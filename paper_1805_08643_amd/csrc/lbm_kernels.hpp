@@ -49,49 +49,110 @@ template <class T> __device__ inline T *at(T *base, uint32_t boff) {
     return reinterpret_cast<T *>(reinterpret_cast<char *>(base) + boff);
 }
 
-// Pull the 19 populations arriving at (x, y, z).  Byte offsets of one
-// direction plane must fit in 32 bits (N * sizeof(T) < 4 GiB).
+// Byte offsets, within one z-plane of one direction, of the nine (y, x)
+// neighbours a pull reads: computed once per thread; the plane part of every
+// address is wave-uniform and lives in scalar registers.
+struct NbOff {
+    uint32_t c;             // (y, x)
+    uint32_t xm, xp;        // (y, x-1), (y, x+1)
+    uint32_t ym, yp;        // (y-1, x), (y+1, x)
+    uint32_t mm, pp, pm, mp;  // (y-1, x-1), (y+1, x+1), (y+1, x-1), (y-1, x+1)
+    __device__ inline void set(int x, int xm_, int xp_, int y, int ym_, int yp_, int nx, uint32_t E) {
+        const uint32_t rb = (uint32_t)nx * E;
+        const uint32_t ry = (uint32_t)y * rb, rym = (uint32_t)ym_ * rb, ryp = (uint32_t)yp_ * rb;
+        const uint32_t bx = (uint32_t)x * E, bxm = (uint32_t)xm_ * E, bxp = (uint32_t)xp_ * E;
+        c = ry + bx;
+        xm = ry + bxm;
+        xp = ry + bxp;
+        ym = rym + bx;
+        yp = ryp + bx;
+        mm = rym + bxm;
+        pp = ryp + bxp;
+        pm = ryp + bxm;
+        mp = rym + bxp;
+    }
+};
+
+// Buffer descriptors over a population array: four groups of five direction
+// planes (the last group has four), so every offset within a group fits the
+// 32-bit scalar offset when 5 N sizeof(T) < 4 GiB.  Direction d lives in
+// group d / 5 at scalar offset (d % 5) * N sizeof(T) + plane offset.
+struct PopBuf {
+    rsrc_t r[4];
+    uint32_t dbytes;  // N * sizeof(T): bytes of one direction plane
+    template <class T> __device__ inline void set(const T *base, size_t N) {
+        dbytes = (uint32_t)(N * sizeof(T));
+        for (int k = 0; k < 4; ++k) {
+            const int nd = k < 3 ? 5 : 4;
+            r[k] = make_rsrc(base + (size_t)(5 * k) * N, (uint32_t)nd * dbytes);
+        }
+    }
+    __device__ inline rsrc_t of(int d) const { return r[d / 5]; }
+    __device__ inline uint32_t so(int d, uint32_t plane) const { return (uint32_t)(d % 5) * dbytes + plane; }
+};
+
+// Pull the 19 populations arriving at the node with offsets o in plane z:
+// direction a comes from (x - e_a), i.e. plane z - e_az, or, across a
+// half-way bounce-back wall, from direction opp(a) at the node itself.
+// PB = bytes of one z-plane of one direction.
 template <int S, bool WALL>
-__device__ inline void pull(const typename Storage<S>::T *__restrict__ A, size_t N, int nx, int ny,
-                            int nz, int x, int xm, int xp, int y, int ym, int yp, int z,
+__device__ inline void pull(const PopBuf &A, int nz, uint32_t PB, int z, const NbOff &o,
                             const Phys<typename Storage<S>::R> &P, typename Storage<S>::R f[Q]) {
     using ST = Storage<S>;
-    using T = typename ST::T;
-    constexpr uint32_t E = sizeof(T);
     const bool bot = WALL && z == 0;
     const bool top = WALL && z == nz - 1;
-    const int zm = WALL ? z - 1 : (z == 0 ? nz - 1 : z - 1);
-    const int zq = WALL ? z + 1 : (z == nz - 1 ? 0 : z + 1);
-    const uint32_t rowb = (uint32_t)nx * E;
-    const uint32_t pc = (uint32_t)z * ny, pm = (uint32_t)zm * ny, pq = (uint32_t)zq * ny;
-    const uint32_t r_c = (pc + y) * rowb, r_cm = (pc + ym) * rowb, r_cp = (pc + yp) * rowb;
-    const uint32_t r_m = (pm + y) * rowb, r_mm = (pm + ym) * rowb, r_mp = (pm + yp) * rowb;
-    const uint32_t r_q = (pq + y) * rowb, r_qm = (pq + ym) * rowb, r_qp = (pq + yp) * rowb;
-    const uint32_t bx = (uint32_t)x * E, bxm = (uint32_t)xm * E, bxp = (uint32_t)xp * E;
-    const uint32_t own = r_c + bx;
-#define LBM_LD(d, boff) ST::load(at(A + (size_t)(d) * N, (boff)), P.sh(d), P.hsi)
-    f[0] = LBM_LD(0, own);
-    f[1] = LBM_LD(1, r_c + bxm);
-    f[2] = LBM_LD(2, r_c + bxp);
-    f[3] = LBM_LD(3, r_cm + bx);
-    f[4] = LBM_LD(4, r_cp + bx);
-    f[7] = LBM_LD(7, r_cm + bxm);
-    f[8] = LBM_LD(8, r_cp + bxp);
-    f[9] = LBM_LD(9, r_cp + bxm);
-    f[10] = LBM_LD(10, r_cm + bxp);
-    // e_z = +1 arrive from z - 1 (or bounce back at the bottom wall)
-    f[5] = bot ? LBM_LD(6, own) : LBM_LD(5, r_m + bx);
-    f[11] = bot ? LBM_LD(12, own) : LBM_LD(11, r_m + bxm);
-    f[14] = bot ? LBM_LD(13, own) : LBM_LD(14, r_m + bxp);
-    f[15] = bot ? LBM_LD(16, own) : LBM_LD(15, r_mm + bx);
-    f[18] = bot ? LBM_LD(17, own) : LBM_LD(18, r_mp + bx);
-    // e_z = -1 arrive from z + 1 (or bounce back at the top wall)
-    f[6] = top ? LBM_LD(5, own) : LBM_LD(6, r_q + bx);
-    f[12] = top ? LBM_LD(11, own) : LBM_LD(12, r_q + bxp);
-    f[13] = top ? LBM_LD(14, own) : LBM_LD(13, r_q + bxm);
-    f[16] = top ? LBM_LD(15, own) : LBM_LD(16, r_qp + bx);
-    f[17] = top ? LBM_LD(18, own) : LBM_LD(17, r_qm + bx);
+    const int zm = WALL ? (bot ? z : z - 1) : (z == 0 ? nz - 1 : z - 1);
+    const int zq = WALL ? (top ? z : z + 1) : (z == nz - 1 ? 0 : z + 1);
+    const uint32_t pc = (uint32_t)z * PB, pm = (uint32_t)zm * PB, pq = (uint32_t)zq * PB;
+#define LBM_LD(d, plane, off) ST::ldb(A.of(d), (off), A.so((d), (plane)), P.sh(d), P.hsi)
+    f[0] = LBM_LD(0, pc, o.c);
+    f[1] = LBM_LD(1, pc, o.xm);
+    f[2] = LBM_LD(2, pc, o.xp);
+    f[3] = LBM_LD(3, pc, o.ym);
+    f[4] = LBM_LD(4, pc, o.yp);
+    f[7] = LBM_LD(7, pc, o.mm);
+    f[8] = LBM_LD(8, pc, o.pp);
+    f[9] = LBM_LD(9, pc, o.pm);
+    f[10] = LBM_LD(10, pc, o.mp);
+    if (!bot) {  // e_z = +1 arrive from z - 1
+        f[5] = LBM_LD(5, pm, o.c);
+        f[11] = LBM_LD(11, pm, o.xm);
+        f[14] = LBM_LD(14, pm, o.xp);
+        f[15] = LBM_LD(15, pm, o.ym);
+        f[18] = LBM_LD(18, pm, o.yp);
+    } else {  // bounce back at the bottom wall
+        f[5] = LBM_LD(6, pc, o.c);
+        f[11] = LBM_LD(12, pc, o.c);
+        f[14] = LBM_LD(13, pc, o.c);
+        f[15] = LBM_LD(16, pc, o.c);
+        f[18] = LBM_LD(17, pc, o.c);
+    }
+    if (!top) {  // e_z = -1 arrive from z + 1
+        f[6] = LBM_LD(6, pq, o.c);
+        f[12] = LBM_LD(12, pq, o.xp);
+        f[13] = LBM_LD(13, pq, o.xm);
+        f[16] = LBM_LD(16, pq, o.yp);
+        f[17] = LBM_LD(17, pq, o.ym);
+    } else {  // bounce back at the top wall
+        f[6] = LBM_LD(5, pc, o.c);
+        f[12] = LBM_LD(11, pc, o.c);
+        f[13] = LBM_LD(14, pc, o.c);
+        f[16] = LBM_LD(15, pc, o.c);
+        f[17] = LBM_LD(18, pc, o.c);
+    }
 #undef LBM_LD
+}
+
+// Pull at an arbitrary node (readback and diagnostics kernels).
+template <int S, bool WALL>
+__device__ inline void pull_at(const typename Storage<S>::T *__restrict__ A, const GridDesc &g, int x, int y, int z,
+                               const Phys<typename Storage<S>::R> &P, typename Storage<S>::R f[Q]) {
+    NbOff o;
+    o.set(x, wrapi(x - 1, g.nx), wrapi(x + 1, g.nx), y, wrapi(y - 1, g.ny), wrapi(y + 1, g.ny), g.nx,
+          (uint32_t)sizeof(typename Storage<S>::T));
+    PopBuf pb;
+    pb.set(A, (size_t)g.N);
+    pull<S, WALL>(pb, g.nz, (uint32_t)((size_t)g.nx * g.ny * sizeof(typename Storage<S>::T)), z, o, P, f);
 }
 
 template <class R> __device__ inline R sum19(const R f[Q]) {
@@ -121,9 +182,30 @@ __device__ inline void psi_stencil(const R *__restrict__ lo, const R *__restrict
     az = e * (pzp - pzm) + d * ((hxp - lxm) - (lxp - hxm) + (hyp - lym) - (lyp - hym));
 }
 
+// Block barrier that orders LDS only: global loads issued before it (the
+// prefetch of the next plane) and stores of the previous plane stay in
+// flight across it.
+__device__ inline void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+#ifndef LBM_PREFETCH
+// Software prefetch of plane z+2 during the collision of plane z; it holds a
+// third plane of populations in registers and measured no faster, so it is
+// off by default.
+#define LBM_PREFETCH 0
+#endif
+
 // One block's z-march over a tile.  ps: LDS ring of 4 planes of
 // (ty + 2) x (tx + 2) psi values.
-template <int S, int OP, bool WALL>
+//
+// Per plane z the block (i) finishes plane z+1: densities of its interior
+// and halo pulls -> psi -> LDS; (ii) barriers; (iii) issues the loads of plane
+// z+2 (PF) so they are in flight during (iv) the collision and store of
+// plane z, whose populations were pulled two iterations earlier.
+template <int S, int OP, bool WALL, bool PF>
 __device__ inline void tile_march(const typename Storage<S>::T *__restrict__ A,
                                   typename Storage<S>::T *__restrict__ B,
                                   const typename Storage<S>::R *__restrict__ gpsi, const GridDesc &g,
@@ -151,9 +233,14 @@ __device__ inline void tile_march(const typename Storage<S>::T *__restrict__ A,
     const bool need_in = inner && lx <= nx - x0 && ly <= ny - y0;
     const bool active = inner && x0 + lx < nx && y0 + ly < ny;
     const int gx = wrapi(x0 + lx, nx), gy = wrapi(y0 + ly, ny);
-    const int gxm = wrapi(gx - 1, nx), gxp = wrapi(gx + 1, nx);
-    const int gym = wrapi(gy - 1, ny), gyp = wrapi(gy + 1, ny);
     const int cin = (ly + 1) * SX + lx + 1;
+    constexpr uint32_t E = sizeof(typename ST::T);
+    const uint32_t PB = (uint32_t)((size_t)nx * ny * E);  // bytes of one z-plane of one direction
+    PopBuf bA, bB;
+    bA.set(A, N);
+    bB.set(B, N);
+    NbOff oin;
+    oin.set(gx, wrapi(gx - 1, nx), wrapi(gx + 1, nx), gy, wrapi(gy - 1, ny), wrapi(gy + 1, ny), nx, E);
 
     // Halo ring position of this thread (top row, bottom row, left, right).
     const int nh = 2 * SX + 2 * TY;
@@ -177,40 +264,47 @@ __device__ inline void tile_march(const typename Storage<S>::T *__restrict__ A,
         halo = hlx <= nx - x0 && hly <= ny - y0;
     }
     const int hx = wrapi(x0 + hlx, nx), hy = wrapi(y0 + hly, ny);
-    const int hxm = wrapi(hx - 1, nx), hxp = wrapi(hx + 1, nx);
-    const int hym = wrapi(hy - 1, ny), hyp = wrapi(hy + 1, ny);
     const int chl = (hly + 1) * SX + hlx + 1;
+    NbOff oh;
+    oh.set(hx, wrapi(hx - 1, nx), wrapi(hx + 1, nx), hy, wrapi(hy - 1, ny), wrapi(hy + 1, ny), nx, E);
 
-    R fc[Q], fn[Q];
+    R fc[Q], fn[Q], fh[Q];
+    R fp[PF ? Q : 1];
     R rc = (R)1, rn = (R)1;
 
-    auto stage = [&](int zp, R *slot, R *fkeep, R &rkeep) {
+    // Issue the loads of plane zp (interior into fi, halo into fhh).
+    auto issue = [&](int zp, R *fi, R *fhh) {
+        if (WALL && (zp < 0 || zp >= nz)) return;
+        const int zw = WALL ? zp : wrapi(zp, nz);
+        if (need_in) pull<S, WALL>(bA, nz, PB, zw, oin, P, fi);
+        if (halo) pull<S, WALL>(bA, nz, PB, zw, oh, P, fhh);
+    };
+    // Densities and psi of plane zp into its LDS slot.
+    auto finish = [&](int zp, R *slot, const R *fi, const R *fhh, R &rk) {
         if (WALL && (zp < 0 || zp >= nz)) {
             const R *gp = gpsi + (zp < 0 ? 0 : (size_t)nx * ny);
             if (need_in) slot[cin] = gp[(size_t)gy * nx + gx];
             if (halo) slot[chl] = gp[(size_t)hy * nx + hx];
             return;
         }
-        const int zw = WALL ? zp : wrapi(zp, nz);
         if (need_in) {
-            pull<S, WALL>(A, N, nx, ny, nz, gx, gxm, gxp, gy, gym, gyp, zw, P, fkeep);
-            rkeep = sum19<R>(fkeep);
-            slot[cin] = pseudo_psi<R>(P, rkeep);
+            rk = sum19<R>(fi);
+            slot[cin] = pseudo_psi<R>(P, rk);
         }
-        if (halo) {
-            R fh[Q];
-            pull<S, WALL>(A, N, nx, ny, nz, hx, hxm, hxp, hy, hym, hyp, zw, P, fh);
-            slot[chl] = pseudo_psi<R>(P, sum19<R>(fh));
-        }
+        if (halo) slot[chl] = pseudo_psi<R>(P, sum19<R>(fhh));
     };
-
     auto slot_of = [&](int z) { return ps + ((z - zb + 1) & 3) * SP; };
 
-    stage(zb - 1, slot_of(zb - 1), fn, rn);
-    stage(zb, slot_of(zb), fc, rc);
+    issue(zb - 1, fn, fh);
+    finish(zb - 1, slot_of(zb - 1), fn, fh, rn);
+    issue(zb, fc, fh);
+    finish(zb, slot_of(zb), fc, fh, rc);
+    if (PF) issue(zb + 1, fn, fh);
     for (int z = zb; z < ze; ++z) {
-        stage(z + 1, slot_of(z + 1), fn, rn);
-        __syncthreads();
+        if (!PF) issue(z + 1, fn, fh);
+        finish(z + 1, slot_of(z + 1), fn, fh, rn);
+        lds_barrier();
+        if (PF && z + 2 <= ze) issue(z + 2, fp, fh);
         if (active) {
             R ax, ay, az;
             const R *mid = slot_of(z);
@@ -221,15 +315,25 @@ __device__ inline void tile_march(const typename Storage<S>::T *__restrict__ A,
             const R Fz = mG_psi * az + rc * P.gz;
             const R acc2 = ax * ax + ay * ay + az * az;
             collide<R, OP>(fc, rc, Fx, Fy, Fz, acc2, P);
-            const uint32_t own = (((uint32_t)z * ny + gy) * nx + gx) * (uint32_t)sizeof(typename ST::T);
+            const uint32_t pz = (uint32_t)z * PB;
 #pragma unroll
-            for (int a = 0; a < Q; ++a) ST::store(at(B + (size_t)a * N, own), fc[a], P.sh(a), P.hs);
+            for (int a = 0; a < Q; ++a) ST::stb(fc[a], bB.of(a), oin.c, bB.so(a, pz), P.shh(a), P.hs);
         }
 #pragma unroll
         for (int a = 0; a < Q; ++a) fc[a] = fn[a];
         rc = rn;
+        if (PF) {
+#pragma unroll
+            for (int a = 0; a < Q; ++a) fn[a] = fp[PF ? a : 0];
+        }
     }
 }
+
+// Prefetching holds a third plane of populations in registers: on for the
+// 4-byte and 2-byte storages, off for FP64 where it would spill.
+template <int S> struct PrefetchOf {
+    static constexpr bool value = LBM_PREFETCH && S != ST_F64;
+};
 
 constexpr int STEP_MAX_THREADS = 512;
 
@@ -244,7 +348,7 @@ __global__ void __launch_bounds__(STEP_MAX_THREADS)
     if (tile >= g.ntiles) return;
     Phys<R> P;
     P.load(pd);
-    tile_march<S, OP, WALL>(A, B, gpsi, g, P, tile, ps);
+    tile_march<S, OP, WALL, PrefetchOf<S>::value>(A, B, gpsi, g, P, tile, ps);
 }
 
 // ---------------------------------------------------------------------------
@@ -287,8 +391,8 @@ __global__ void __launch_bounds__(STEP_MAX_THREADS)
         P.load(rd.pd);
         const T *src = reinterpret_cast<const T *>(ws + (parity ? rd.offB : rd.offA));
         T *dst = reinterpret_cast<T *>(ws + (parity ? rd.offA : rd.offB));
-        tile_march<S, OP, false>(src, dst, nullptr, g, P, item - rd.tile_begin, ps);
-        __syncthreads();  // the next item reuses the LDS ring
+        tile_march<S, OP, false, PrefetchOf<S>::value>(src, dst, nullptr, g, P, item - rd.tile_begin, ps);
+        lds_barrier();  // the next item reuses the LDS ring
     }
 }
 
@@ -312,8 +416,7 @@ __global__ void k_wall_rho(const typename Storage<S>::T *__restrict__ A,
     const int x = rem % nx, y = rem / nx;
     const int z = k == 0 ? 0 : (k == 1 ? 1 : (k == 2 ? nz - 2 : nz - 1));
     R f[Q];
-    pull<S, true>(A, (size_t)g.N, nx, ny, nz, x, wrapi(x - 1, nx), wrapi(x + 1, nx), y, wrapi(y - 1, ny),
-                  wrapi(y + 1, ny), z, P, f);
+    pull_at<S, true>(A, g, x, y, z, P, f);
     rho_w[i] = sum19<R>(f);
 }
 
@@ -352,8 +455,7 @@ __global__ void k_psi_full(const typename Storage<S>::T *__restrict__ A,
          i += (long long)gridDim.x * blockDim.x) {
         const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((long long)nx * ny));
         R f[Q];
-        pull<S, WALL>(A, (size_t)g.N, nx, ny, nz, x, wrapi(x - 1, nx), wrapi(x + 1, nx), y, wrapi(y - 1, ny),
-                      wrapi(y + 1, ny), z, P, f);
+        pull_at<S, WALL>(A, g, x, y, z, P, f);
         psi[i] = pseudo_psi<R>(P, sum19<R>(f));
     }
 }
@@ -384,8 +486,7 @@ __device__ inline void node_macro(const typename Storage<S>::T *__restrict__ A,
     using R = typename Storage<S>::R;
     const int nx = g.nx, ny = g.ny;
     R f[Q];
-    pull<S, WALL>(A, (size_t)g.N, nx, ny, g.nz, x, wrapi(x - 1, nx), wrapi(x + 1, nx), y, wrapi(y - 1, ny),
-                  wrapi(y + 1, ny), z, P, f);
+    pull_at<S, WALL>(A, g, x, y, z, P, f);
     finite = true;
 #pragma unroll
     for (int a = 0; a < Q; ++a) finite = finite && isfinite(f[a]);
@@ -449,8 +550,7 @@ __global__ void k_read_pops(const typename Storage<S>::T *__restrict__ A, double
          i += (long long)gridDim.x * blockDim.x) {
         const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((long long)nx * ny));
         R v[Q];
-        pull<S, WALL>(A, (size_t)g.N, nx, ny, g.nz, x, wrapi(x - 1, nx), wrapi(x + 1, nx), y, wrapi(y - 1, ny),
-                      wrapi(y + 1, ny), z, P, v);
+        pull_at<S, WALL>(A, g, x, y, z, P, v);
 #pragma unroll
         for (int a = 0; a < Q; ++a) f[(size_t)a * g.N + i] = (double)v[a];
     }
@@ -476,7 +576,7 @@ __device__ inline void scatter_node(typename Storage<S>::T *__restrict__ A, cons
             sz = wrapi(sz, g.nz);
             idx = ((size_t)sz * g.ny + wrapi(y - ey(a), g.ny)) * g.nx + wrapi(x - ex(a), g.nx);
         }
-        ST::store(A + (size_t)d * g.N + idx, v[a], P.sh(a), P.hs);
+        ST::store(A + (size_t)d * g.N + idx, v[a], P.shh(a), P.hs);
     }
 }
 

@@ -7,7 +7,7 @@ STEP_TILES = {
     ("droplet_32", "f64"): (32, 8, 8),
     ("laplace_128", "f64"): (64, 4, 16),
     ("laplace_128", "f32"): (64, 4, 16),
-    ("two_droplets_256", "f64"): (64, 4, 32),
+    ("two_droplets_256", "f64"): (128, 4, 64),
     ("two_droplets_256", "f32"): (64, 4, 32),
     ("two_droplets_256", "f16s"): (64, 4, 32),
     ("sessile_384x384x192", "f32"): (64, 4, 32),

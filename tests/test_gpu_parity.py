@@ -175,8 +175,9 @@ def test_f16s_parity(name):
 
 def test_f16_storage_format_round_trip():
     """Populations written through the C ABI and read back equal the stated
-    format exactly: binary16 round-to-nearest-even of (f - w rho_ref) 2^e
-    evaluated in FP32, then widened back."""
+    format exactly: v = fbar rounded to FP32, h = (v - w rho_ref) 2^e
+    evaluated exactly and rounded once (nearest even) to binary16; reading
+    gives h 2^-e + w rho_ref rounded once to FP32."""
     _need_gpu()
     cfg, init = li.c3_two_droplets(n=24)
     cfg = dict(cfg, storage="f16s", rho_ref=init["rho_V"], f16_exp=f16_exp_for(1.25 * init["rho_L"]))
@@ -186,10 +187,11 @@ def test_f16_storage_format_round_trip():
     lat.write_populations(f)
     got = lat.read_populations().cpu().numpy()
     lat.close()
-    hs = np.float32(2.0 ** cfg["f16_exp"])
-    shift = (W_CLASS * cfg["rho_ref"]).astype(np.float32)[:, None]
-    h16 = ((f.astype(np.float32) - shift) * hs).astype(np.float16)
-    want = (h16.astype(np.float32) * np.float32(1.0 / hs) + shift).astype(np.float64)
+    hs = 2.0 ** cfg["f16_exp"]
+    shift = (W_CLASS * cfg["rho_ref"]).astype(np.float32).astype(np.float64)[:, None]
+    v = f.astype(np.float32).astype(np.float64)
+    h16 = ((v - shift) * hs).astype(np.float16)  # exact in FP64, one rounding to binary16
+    want = (h16.astype(np.float64) / hs + shift).astype(np.float32).astype(np.float64)
     assert np.array_equal(got, want)
 
 
