@@ -185,9 +185,18 @@ lbm_status lbm_set_tile(lbm_ctx *ctx, const lbm_tile *t);
 lbm_status lbm_get_tile(const lbm_ctx *ctx, lbm_tile *t);
 lbm_status lbm_autotune(lbm_ctx *ctx, int32_t trials, lbm_tile *best);
 
-/* Average device time of the fused step kernel over the steps launched
- * since the last call, measured with HIP events on the context's stream
- * when timing is enabled (lbm_set_timing(ctx, 1)).  Synchronises. */
+/* Step implementation.  LBM_STEP_FUSED (default): one kernel per step, tiles
+ * marching in z with psi and its halo in LDS.  LBM_STEP_SLABS: per z-slab of
+ * slab_planes planes, a psi pass then a collide pass that re-reads the slab
+ * (sized to stay in the last-level cache) and reads psi from a global array.
+ * Both give the same populations bit for bit. */
+enum { LBM_STEP_FUSED = 0, LBM_STEP_SLABS = 1 };
+lbm_status lbm_set_step_mode(lbm_ctx *ctx, int32_t mode, int32_t slab_planes);
+
+/* Average device time of one step's kernels (fused mode: the step kernel;
+ * slab mode: the psi and collide passes of all slabs) over the steps launched
+ * since the last call, measured with HIP events on the context's stream when
+ * timing is enabled (lbm_set_timing(ctx, 1)).  Synchronises. */
 lbm_status lbm_set_timing(lbm_ctx *ctx, int32_t enable);
 lbm_status lbm_kernel_time(lbm_ctx *ctx, double *avg_ms, int64_t *launches);
 

@@ -92,6 +92,7 @@ SIGNATURES = {
     "lbm_set_tile": (_i32, [_vp, _P(LbmTile)]),
     "lbm_get_tile": (_i32, [_vp, _P(LbmTile)]),
     "lbm_autotune": (_i32, [_vp, _i32, _P(LbmTile)]),
+    "lbm_set_step_mode": (_i32, [_vp, _i32, _i32]),
     "lbm_set_timing": (_i32, [_vp, _i32]),
     "lbm_kernel_time": (_i32, [_vp, _dp, _P(_i64)]),
     "lbm_step_count": (_i64, [_vp]),
@@ -227,6 +228,10 @@ def lbm_autotune(ctx, trials):
     t = LbmTile()
     _call("lbm_autotune", _vp(ctx), trials, ctypes.byref(t))
     return (t.tx, t.ty, t.cz)
+
+
+def lbm_set_step_mode(ctx, mode, slab_planes):
+    _call("lbm_set_step_mode", _vp(ctx), int(mode), int(slab_planes))
 
 
 def lbm_set_timing(ctx, enable):
@@ -405,6 +410,10 @@ class Lattice:
 
     def autotune(self, trials=3):
         return lbm_autotune(self.ctx, trials)
+
+    def set_step_mode(self, mode, slab_planes=32):
+        """mode: "fused" or "slabs"."""
+        lbm_set_step_mode(self.ctx, {"fused": 0, "slabs": 1}[mode], slab_planes)
 
     def set_timing(self, on=True):
         lbm_set_timing(self.ctx, on)

@@ -220,6 +220,8 @@ struct lbm_ctx {
     bool timing = false;
     std::vector<hipEvent_t> ev;  // start/stop pairs
     size_t nev = 0;              // pairs recorded since last read
+    int mode = LBM_STEP_FUSED;
+    int slab = 32;
 
     void *state() const { return ws + (cur ? L.B : L.A); }
     void *other() const { return ws + (cur ? L.A : L.B); }
@@ -291,6 +293,33 @@ lbm_status launch_step(lbm_ctx *c, const GridDesc &g, const void *src, void *dst
     });
 }
 
+lbm_status launch_slabs(lbm_ctx *c, const void *src, void *dst) {
+    return dispatch(c, [&](auto S, auto O, auto W) -> lbm_status {
+        using T = typename Storage<S.value>::T;
+        using R = typename Storage<S.value>::R;
+        const int nz = c->p.nz;
+        const long long plane = (long long)c->p.nx * c->p.ny;
+        auto psi_pass = [&](int za, int zb) {
+            if (zb <= za) return;
+            hipLaunchKernelGGL((k_psi_planes<S.value, W.value>), dim3(grid1d(plane * (zb - za), 256)), dim3(256), 0,
+                               c->stream, (const T *)src, (R *)c->psi(), c->g, c->pd, za, zb);
+        };
+        // psi of the planes below the first slab: plane 0, and plane nz-1 for
+        // the periodic wrap (walls use the ghost layer instead).
+        psi_pass(0, 1);
+        if (!W.value && nz > 1) psi_pass(nz - 1, nz);
+        for (int z0 = 0; z0 < nz; z0 += c->slab) {
+            const int z1 = std::min(nz, z0 + c->slab);
+            psi_pass(z0 + 1, std::min(z1 + 1, nz));
+            hipLaunchKernelGGL((k_collide_planes<S.value, O.value, W.value>), dim3(grid1d(plane * (z1 - z0), 256)),
+                               dim3(256), 0, c->stream, (const T *)src, (T *)dst, (const R *)c->psi(),
+                               (const R *)c->gpsi(), c->g, c->pd, z0, z1);
+        }
+        HIP_TRY(hipGetLastError());
+        return LBM_OK;
+    });
+}
+
 lbm_status timed_event(lbm_ctx *c, size_t k) {
     while (c->ev.size() <= k) {
         hipEvent_t e;
@@ -307,7 +336,11 @@ lbm_status one_step(lbm_ctx *c) {
     if (c->timing) {
         if ((s = timed_event(c, 2 * c->nev))) return s;
     }
-    if ((s = launch_step(c, c->g, c->state(), c->other()))) return s;
+    if (c->mode == LBM_STEP_SLABS) {
+        if ((s = launch_slabs(c, c->state(), c->other()))) return s;
+    } else if ((s = launch_step(c, c->g, c->state(), c->other()))) {
+        return s;
+    }
     if (c->timing) {
         if ((s = timed_event(c, 2 * c->nev + 1))) return s;
         ++c->nev;
@@ -629,6 +662,15 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t trials, lbm_tile *best) {
     c->tile = bt;
     fill_grid(c->g, c->p, c->tile);
     if (best) *best = bt;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_step_mode(lbm_ctx *c, int32_t mode, int32_t slab_planes) {
+    if (!c) return fail(LBM_ERR_INVALID_ARG, "ctx is NULL");
+    if (mode != LBM_STEP_FUSED && mode != LBM_STEP_SLABS) return fail(LBM_ERR_INVALID_ARG, "unknown step mode %d", mode);
+    if (slab_planes < 1) return fail(LBM_ERR_INVALID_ARG, "slab_planes < 1");
+    c->mode = mode;
+    c->slab = slab_planes;
     return LBM_OK;
 }
 

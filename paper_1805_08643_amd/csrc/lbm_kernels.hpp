@@ -191,21 +191,16 @@ __device__ inline void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-#ifndef LBM_PREFETCH
-// Software prefetch of plane z+2 during the collision of plane z; it holds a
-// third plane of populations in registers and measured no faster, so it is
-// off by default.
-#define LBM_PREFETCH 0
-#endif
-
 // One block's z-march over a tile.  ps: LDS ring of 4 planes of
 // (ty + 2) x (tx + 2) psi values.
 //
-// Per plane z the block (i) finishes plane z+1: densities of its interior
-// and halo pulls -> psi -> LDS; (ii) barriers; (iii) issues the loads of plane
-// z+2 (PF) so they are in flight during (iv) the collision and store of
-// plane z, whose populations were pulled two iterations earlier.
-template <int S, int OP, bool WALL, bool PF>
+// Per plane z the block (i) pulls plane z+1 for its interior columns and its
+// halo ring, all loads in flight together; (ii) turns the densities into psi
+// in LDS; (iii) barriers; (iv) collides and stores plane z, whose
+// populations were pulled one iteration earlier and stayed in registers.
+// (Prefetching plane z+2 before the collision, for the whole tile or for the
+// halo only, measured slower on MI355X.)
+template <int S, int OP, bool WALL>
 __device__ inline void tile_march(const typename Storage<S>::T *__restrict__ A,
                                   typename Storage<S>::T *__restrict__ B,
                                   const typename Storage<S>::R *__restrict__ gpsi, const GridDesc &g,
@@ -269,42 +264,39 @@ __device__ inline void tile_march(const typename Storage<S>::T *__restrict__ A,
     oh.set(hx, wrapi(hx - 1, nx), wrapi(hx + 1, nx), hy, wrapi(hy - 1, ny), wrapi(hy + 1, ny), nx, E);
 
     R fc[Q], fn[Q], fh[Q];
-    R fp[PF ? Q : 1];
     R rc = (R)1, rn = (R)1;
 
     // Issue the loads of plane zp (interior into fi, halo into fhh).
-    auto issue = [&](int zp, R *fi, R *fhh) {
+    auto issue = [&](int zp, R *fi, R *fhh, bool do_in, bool do_halo) {
         if (WALL && (zp < 0 || zp >= nz)) return;
         const int zw = WALL ? zp : wrapi(zp, nz);
-        if (need_in) pull<S, WALL>(bA, nz, PB, zw, oin, P, fi);
-        if (halo) pull<S, WALL>(bA, nz, PB, zw, oh, P, fhh);
+        if (do_in && need_in) pull<S, WALL>(bA, nz, PB, zw, oin, P, fi);
+        if (do_halo && halo) pull<S, WALL>(bA, nz, PB, zw, oh, P, fhh);
     };
     // Densities and psi of plane zp into its LDS slot.
-    auto finish = [&](int zp, R *slot, const R *fi, const R *fhh, R &rk) {
+    auto finish = [&](int zp, R *slot, const R *fi, const R *fhh, R &rk, bool do_in, bool do_halo) {
         if (WALL && (zp < 0 || zp >= nz)) {
             const R *gp = gpsi + (zp < 0 ? 0 : (size_t)nx * ny);
-            if (need_in) slot[cin] = gp[(size_t)gy * nx + gx];
-            if (halo) slot[chl] = gp[(size_t)hy * nx + hx];
+            if (do_in && need_in) slot[cin] = gp[(size_t)gy * nx + gx];
+            if (do_halo && halo) slot[chl] = gp[(size_t)hy * nx + hx];
             return;
         }
-        if (need_in) {
+        if (do_in && need_in) {
             rk = sum19<R>(fi);
             slot[cin] = pseudo_psi<R>(P, rk);
         }
-        if (halo) slot[chl] = pseudo_psi<R>(P, sum19<R>(fhh));
+        if (do_halo && halo) slot[chl] = pseudo_psi<R>(P, sum19<R>(fhh));
     };
     auto slot_of = [&](int z) { return ps + ((z - zb + 1) & 3) * SP; };
 
-    issue(zb - 1, fn, fh);
-    finish(zb - 1, slot_of(zb - 1), fn, fh, rn);
-    issue(zb, fc, fh);
-    finish(zb, slot_of(zb), fc, fh, rc);
-    if (PF) issue(zb + 1, fn, fh);
+    issue(zb - 1, fn, fh, true, true);
+    finish(zb - 1, slot_of(zb - 1), fn, fh, rn, true, true);
+    issue(zb, fc, fh, true, true);
+    finish(zb, slot_of(zb), fc, fh, rc, true, true);
     for (int z = zb; z < ze; ++z) {
-        if (!PF) issue(z + 1, fn, fh);
-        finish(z + 1, slot_of(z + 1), fn, fh, rn);
+        issue(z + 1, fn, fh, true, true);
+        finish(z + 1, slot_of(z + 1), fn, fh, rn, true, true);
         lds_barrier();
-        if (PF && z + 2 <= ze) issue(z + 2, fp, fh);
         if (active) {
             R ax, ay, az;
             const R *mid = slot_of(z);
@@ -322,23 +314,26 @@ __device__ inline void tile_march(const typename Storage<S>::T *__restrict__ A,
 #pragma unroll
         for (int a = 0; a < Q; ++a) fc[a] = fn[a];
         rc = rn;
-        if (PF) {
-#pragma unroll
-            for (int a = 0; a < Q; ++a) fn[a] = fp[PF ? a : 0];
-        }
     }
 }
 
-// Prefetching holds a third plane of populations in registers: on for the
-// 4-byte and 2-byte storages, off for FP64 where it would spill.
-template <int S> struct PrefetchOf {
-    static constexpr bool value = LBM_PREFETCH && S != ST_F64;
-};
-
-constexpr int STEP_MAX_THREADS = 512;
+#ifndef LBM_STEP_MAX_THREADS
+#define LBM_STEP_MAX_THREADS 512
+#endif
+constexpr int STEP_MAX_THREADS = LBM_STEP_MAX_THREADS;
+// Minimum waves per SIMD the step kernels are compiled for (register budget
+// 512 / waves VGPRs); 0 leaves it to the launch bound.
+#ifndef LBM_STEP_WAVES_PER_EU
+#define LBM_STEP_WAVES_PER_EU 0
+#endif
+#if LBM_STEP_WAVES_PER_EU > 0
+#define LBM_STEP_ATTR __launch_bounds__(STEP_MAX_THREADS) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU)))
+#else
+#define LBM_STEP_ATTR __launch_bounds__(STEP_MAX_THREADS)
+#endif
 
 template <int S, int OP, bool WALL>
-__global__ void __launch_bounds__(STEP_MAX_THREADS)
+__global__ void LBM_STEP_ATTR
     k_step(const typename Storage<S>::T *__restrict__ A, typename Storage<S>::T *__restrict__ B,
            const typename Storage<S>::R *__restrict__ gpsi, GridDesc g, PhysD pd) {
     using R = typename Storage<S>::R;
@@ -348,7 +343,7 @@ __global__ void __launch_bounds__(STEP_MAX_THREADS)
     if (tile >= g.ntiles) return;
     Phys<R> P;
     P.load(pd);
-    tile_march<S, OP, WALL, PrefetchOf<S>::value>(A, B, gpsi, g, P, tile, ps);
+    tile_march<S, OP, WALL>(A, B, gpsi, g, P, tile, ps);
 }
 
 // ---------------------------------------------------------------------------
@@ -366,7 +361,7 @@ struct RunDesc {
 };
 
 template <int S, int OP>
-__global__ void __launch_bounds__(STEP_MAX_THREADS)
+__global__ void LBM_STEP_ATTR
     k_batch_step(unsigned char *__restrict__ ws, const RunDesc *__restrict__ runs, int nruns, int total_tiles,
                  int parity) {
     using ST = Storage<S>;
@@ -391,8 +386,91 @@ __global__ void __launch_bounds__(STEP_MAX_THREADS)
         P.load(rd.pd);
         const T *src = reinterpret_cast<const T *>(ws + (parity ? rd.offB : rd.offA));
         T *dst = reinterpret_cast<T *>(ws + (parity ? rd.offA : rd.offB));
-        tile_march<S, OP, false, PrefetchOf<S>::value>(src, dst, nullptr, g, P, item - rd.tile_begin, ps);
+        tile_march<S, OP, false>(src, dst, nullptr, g, P, item - rd.tile_begin, ps);
         lds_barrier();  // the next item reuses the LDS ring
+    }
+}
+
+template <class R>
+__device__ inline R psi_at(const R *__restrict__ psi, const R *__restrict__ gpsi, const GridDesc &g, bool wall,
+                           int x, int y, int z) {
+    x = wrapi(x, g.nx);
+    y = wrapi(y, g.ny);
+    if (wall) {
+        if (z < 0) return gpsi[(size_t)y * g.nx + x];
+        if (z >= g.nz) return gpsi[(size_t)g.nx * g.ny + (size_t)y * g.nx + x];
+    } else {
+        z = wrapi(z, g.nz);
+    }
+    return psi[((size_t)z * g.ny + y) * g.nx + x];
+}
+
+// ---------------------------------------------------------------------------
+// Two-pass step over z-slabs.  Pass A: psi of planes [za, zb) into a global
+// psi array.  Pass B: for planes [za, zb) pull the populations again (the
+// slab was just streamed by pass A and sits in the last-level cache), read
+// the psi stencil from the global array, collide and store.  Every node's
+// arithmetic is the same as in the fused kernel.
+// ---------------------------------------------------------------------------
+template <int S, bool WALL>
+__global__ void __launch_bounds__(256)
+    k_psi_planes(const typename Storage<S>::T *__restrict__ A, typename Storage<S>::R *__restrict__ psi, GridDesc g,
+                 PhysD pd, int za, int zb) {
+    using R = typename Storage<S>::R;
+    Phys<R> P;
+    P.load(pd);
+    const long long plane = (long long)g.nx * g.ny;
+    const long long n = plane * (zb - za);
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x) {
+        const int z = za + (int)(k / plane);
+        const int rem = (int)(k - (long long)(z - za) * plane);
+        const int x = rem % g.nx, y = rem / g.nx;
+        R f[Q];
+        pull_at<S, WALL>(A, g, x, y, z, P, f);
+        psi[(size_t)z * plane + rem] = pseudo_psi<R>(P, sum19<R>(f));
+    }
+}
+
+template <int S, int OP, bool WALL>
+__global__ void __launch_bounds__(256)
+    k_collide_planes(const typename Storage<S>::T *__restrict__ A, typename Storage<S>::T *__restrict__ B,
+                     const typename Storage<S>::R *__restrict__ psi, const typename Storage<S>::R *__restrict__ gpsi,
+                     GridDesc g, PhysD pd, int za, int zb) {
+    using ST = Storage<S>;
+    using R = typename ST::R;
+    Phys<R> P;
+    P.load(pd);
+    const long long plane = (long long)g.nx * g.ny;
+    const long long n = plane * (zb - za);
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x) {
+        const int z = za + (int)(k / plane);
+        const int rem = (int)(k - (long long)(z - za) * plane);
+        const int x = rem % g.nx, y = rem / g.nx;
+        R f[Q];
+        pull_at<S, WALL>(A, g, x, y, z, P, f);
+        const R rho = sum19<R>(f);
+        R acc[3] = {(R)0, (R)0, (R)0};
+        // Same grouping as psi_stencil: axis terms, then the diagonal pairs.
+        auto ps = [&](int dx, int dy, int dz) { return psi_at<R>(psi, gpsi, g, WALL, x + dx, y + dy, z + dz); };
+        const R e = (R)(1.0 / 6.0), d = (R)(1.0 / 12.0);
+        const R pxp = ps(1, 0, 0), pxm = ps(-1, 0, 0), pyp = ps(0, 1, 0), pym = ps(0, -1, 0);
+        const R pzp = ps(0, 0, 1), pzm = ps(0, 0, -1);
+        const R ppx = ps(1, 1, 0), pmm = ps(-1, -1, 0), ppm = ps(1, -1, 0), pmp = ps(-1, 1, 0);
+        const R hxp = ps(1, 0, 1), hxm = ps(-1, 0, 1), hyp = ps(0, 1, 1), hym = ps(0, -1, 1);
+        const R lxp = ps(1, 0, -1), lxm = ps(-1, 0, -1), lyp = ps(0, 1, -1), lym = ps(0, -1, -1);
+        acc[0] = e * (pxp - pxm) + d * ((ppx - pmm) + (ppm - pmp) + (hxp - lxm) + (lxp - hxm));
+        acc[1] = e * (pyp - pym) + d * ((ppx - pmm) - (ppm - pmp) + (hyp - lym) + (lyp - hym));
+        acc[2] = e * (pzp - pzm) + d * ((hxp - lxm) - (lxp - hxm) + (hyp - lym) - (lyp - hym));
+        const R mG_psi = -P.G * psi[(size_t)z * plane + rem];
+        const R Fx = mG_psi * acc[0] + rho * P.gx;
+        const R Fy = mG_psi * acc[1] + rho * P.gy;
+        const R Fz = mG_psi * acc[2] + rho * P.gz;
+        collide<R, OP>(f, rho, Fx, Fy, Fz, acc[0] * acc[0] + acc[1] * acc[1] + acc[2] * acc[2], P);
+        PopBuf bB;
+        bB.set(B, (size_t)g.N);
+        const uint32_t off = (uint32_t)(((size_t)z * plane + rem) * sizeof(typename ST::T));
+#pragma unroll
+        for (int a = 0; a < Q; ++a) ST::stb(f[a], bB.of(a), off, bB.so(a, 0), P.shh(a), P.hs);
     }
 }
 
@@ -450,7 +528,7 @@ __global__ void k_psi_full(const typename Storage<S>::T *__restrict__ A,
     using R = typename Storage<S>::R;
     Phys<R> P;
     P.load(pd);
-    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int nx = g.nx, ny = g.ny;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < g.N;
          i += (long long)gridDim.x * blockDim.x) {
         const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((long long)nx * ny));
@@ -458,20 +536,6 @@ __global__ void k_psi_full(const typename Storage<S>::T *__restrict__ A,
         pull_at<S, WALL>(A, g, x, y, z, P, f);
         psi[i] = pseudo_psi<R>(P, sum19<R>(f));
     }
-}
-
-template <class R>
-__device__ inline R psi_at(const R *__restrict__ psi, const R *__restrict__ gpsi, const GridDesc &g, bool wall,
-                           int x, int y, int z) {
-    x = wrapi(x, g.nx);
-    y = wrapi(y, g.ny);
-    if (wall) {
-        if (z < 0) return gpsi[(size_t)y * g.nx + x];
-        if (z >= g.nz) return gpsi[(size_t)g.nx * g.ny + (size_t)y * g.nx + x];
-    } else {
-        z = wrapi(z, g.nz);
-    }
-    return psi[((size_t)z * g.ny + y) * g.nx + x];
 }
 
 // Node-level macroscopic quantities from the pulled populations and a psi field.
