@@ -98,6 +98,55 @@ def time_steps(lat, steps, warmup, kernel_timing):
     return ms, wall, kms
 
 
+def bench_batch(storage, steps=40, graph_steps=10):
+    """Batched workload: 256 independent periodic droplet runs, L ~ U{32, 48,
+    64, 96}, T/Tc ~ U[0.6, 0.9], tau_nu ~ U[0.6, 1.2] (seed 1805), one
+    persistent launch per step.  Aggregate MLUPS with plain launches, with
+    hipGraph replay, and after the batch autotuner."""
+    import torch
+
+    import lbm_inputs as li
+    from paper_1805_08643_amd.binding import Batch, algorithmic_bytes_per_node, f16_exp_for
+    runs = li.c5_batch()
+    cfgs = [dict(p, storage=storage, rho_ref=init["rho_V"], f16_exp=f16_exp_for(1.25 * init["rho_L"]))
+            for p, init in runs]
+    b = Batch(cfgs)
+    for k, (_, init) in enumerate(runs):
+        b.init_droplets(k, init["droplets"], init["rho_L"], init["rho_V"], init["W"])
+    N = b.nodes
+
+    def timed(graph):
+        b.step(2 * graph_steps, graph)  # warm-up (and graph capture)
+        torch.cuda.synchronize()
+        b.kernel_time()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.step(steps, graph)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        kms, _ = b.kernel_time()
+        return ms, kms
+
+    out = {"runs": len(runs), "nodes": N, "storage": storage}
+    ms, _ = timed(0)
+    out["mlups_plain_launches"] = round(N / (ms * 1e-3) / 1e6, 1)
+    ms, _ = timed(graph_steps)
+    out["mlups_graph"] = round(N / (ms * 1e-3) / 1e6, 1)
+    blocks = b.autotune(3)
+    ms, kms = timed(graph_steps)
+    out["mlups_tuned_graph"] = round(N / (ms * 1e-3) / 1e6, 1)
+    out["tuned_blocks"] = blocks
+    out["ms_per_step"] = round(ms, 4)
+    out["hbm_frac"] = round(algorithmic_bytes_per_node(storage) * N / (kms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
+    d = b.read_fields(0)["rho"]
+    out["finite"] = bool(torch.isfinite(d).all().item())
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    return out
+
+
 def read_traffic(storage, op):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it covers this kernel; None otherwise."""
@@ -192,6 +241,7 @@ def main():
             del l2
             torch.cuda.empty_cache()
         out["variants_mlups"] = var
+        out["batch"] = {st: bench_batch(st) for st in ("f32", "f16s")}
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, init, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -433,6 +433,86 @@ def f16_exp_for(rho_max: float) -> int:
     return int(math.floor(math.log2(2.0 ** 15 / (rho_max / 3.0))))
 
 
+class Batch:
+    """Many independent periodic lattices advanced by one persistent launch per
+    step (common operator and storage), backed by one workspace tensor."""
+
+    def __init__(self, cfgs, device: str = "cuda:0"):
+        torch = _torch()
+        self.cfgs = [dict(c) for c in cfgs]
+        n = len(cfgs)
+        self.params = (LbmParams * n)(*[make_params(c) for c in cfgs])
+        nb = _sz(0)
+        _call("lbm_batch_workspace_bytes", self.params, n, ctypes.byref(nb))
+        self.device = torch.device(device)
+        self.ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        h = _vp()
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        _call("lbm_batch_create", self.params, n, _vp(ptr), nb.value, _vp(st), ctypes.byref(h))
+        self.h = h.value
+
+    def init_droplets(self, run, droplets, rho_L, rho_V, W):
+        arr = _droplet_array(droplets)
+        _call("lbm_batch_init_droplets", _vp(self.h), run, arr, len(droplets), rho_L, rho_V, W)
+
+    def init_fields(self, run, rho, u):
+        torch = _torch()
+        r = torch.as_tensor(rho, dtype=torch.float64).to(self.device).contiguous()
+        v = torch.as_tensor(u, dtype=torch.float64).to(self.device).contiguous()
+        _call("lbm_batch_init_fields", _vp(self.h), run, _vp(r.data_ptr()), _vp(v.data_ptr()))
+        torch.cuda.synchronize(self.device)
+
+    def step(self, n, graph_steps=0):
+        _call("lbm_batch_step", _vp(self.h), int(n), int(graph_steps))
+
+    def read_populations(self, run):
+        torch = _torch()
+        c = self.cfgs[run]
+        f = torch.empty((Q, c["nx"] * c["ny"] * c["nz"]), dtype=torch.float64, device=self.device)
+        _call("lbm_batch_read_populations", _vp(self.h), run, _vp(f.data_ptr()))
+        return f
+
+    def read_fields(self, run):
+        torch = _torch()
+        c = self.cfgs[run]
+        N = c["nx"] * c["ny"] * c["nz"]
+        rho = torch.empty(N, dtype=torch.float64, device=self.device)
+        u = torch.empty((3, N), dtype=torch.float64, device=self.device)
+        p = torch.empty(N, dtype=torch.float64, device=self.device)
+        _call("lbm_batch_read_fields", _vp(self.h), run, _vp(rho.data_ptr()), _vp(u.data_ptr()), _vp(p.data_ptr()))
+        return {"rho": rho, "u": u, "p": p}
+
+    def autotune(self, trials=3):
+        b = _i32(0)
+        _call("lbm_batch_autotune", _vp(self.h), int(trials), ctypes.byref(b))
+        return b.value
+
+    def set_blocks(self, blocks):
+        _call("lbm_batch_set_blocks", _vp(self.h), int(blocks))
+
+    def kernel_time(self):
+        ms = ctypes.c_double(0)
+        n = _i64(0)
+        _call("lbm_batch_kernel_time", _vp(self.h), ctypes.byref(ms), ctypes.byref(n))
+        return ms.value, n.value
+
+    @property
+    def nodes(self):
+        return lib().lbm_batch_nodes(_vp(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            _call("lbm_batch_destroy", _vp(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def storage_bytes(storage: str) -> int:
     return {"f64": 8, "f32": 4, "f16s": 2}[storage]
 

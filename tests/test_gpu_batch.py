@@ -1,8 +1,6 @@
 """Batched runs: one persistent launch per step over many independent
 lattices of uneven size, plain and hipGraph-replayed, against the oracle and
 against single-lattice launches."""
-import ctypes
-
 import numpy as np
 import pytest
 import torch
@@ -15,40 +13,9 @@ from paper_1805_08643_amd.binding import Lattice
 pytestmark = pytest.mark.gpu
 
 
-class Batch:
-    def __init__(self, cfgs):
-        self.cfgs = cfgs
-        n = len(cfgs)
-        self.params = (binding.LbmParams * n)(*[binding.make_params(c) for c in cfgs])
-        nb = ctypes.c_size_t(0)
-        binding.check(binding.lib().lbm_batch_workspace_bytes(self.params, n, ctypes.byref(nb)),
-                      "lbm_batch_workspace_bytes")
-        self.ws = torch.empty(nb.value + 256, dtype=torch.uint8, device="cuda")
-        ptr = (self.ws.data_ptr() + 255) // 256 * 256
-        h = ctypes.c_void_p()
-        st = torch.cuda.current_stream().cuda_stream
-        binding.check(binding.lib().lbm_batch_create(self.params, n, ctypes.c_void_p(ptr), nb.value,
-                                                     ctypes.c_void_p(st), ctypes.byref(h)), "lbm_batch_create")
-        self.h = h
-
-    def init_fields(self, k, rho, u):
-        r = torch.as_tensor(rho, device="cuda").contiguous()
-        v = torch.as_tensor(u, device="cuda").contiguous()
-        binding.check(binding.lib().lbm_batch_init_fields(self.h, k, ctypes.c_void_p(r.data_ptr()),
-                                                          ctypes.c_void_p(v.data_ptr())), "init")
-        torch.cuda.synchronize()
-
-    def step(self, n, graph_steps=0):
-        binding.check(binding.lib().lbm_batch_step(self.h, n, graph_steps), "lbm_batch_step")
-
+class Batch(binding.Batch):
     def pops(self, k):
-        c = self.cfgs[k]
-        f = torch.empty((19, c["nx"] * c["ny"] * c["nz"]), dtype=torch.float64, device="cuda")
-        binding.check(binding.lib().lbm_batch_read_populations(self.h, k, ctypes.c_void_p(f.data_ptr())), "read")
-        return f.cpu().numpy()
-
-    def close(self):
-        binding.check(binding.lib().lbm_batch_destroy(self.h), "destroy")
+        return self.read_populations(k).cpu().numpy()
 
 
 def _runs(storage, sizes=(12, 16, 20, 24, 18), seed=5):
@@ -114,9 +81,7 @@ def test_batch_full_workload_sampled_runs():
     cfgs = [dict(p, storage="f32") for p, _ in runs]
     b = Batch(cfgs)
     for k, (p, init) in enumerate(runs):
-        lib_d = binding._droplet_array(init["droplets"])
-        binding.check(binding.lib().lbm_batch_init_droplets(b.h, k, lib_d, 1, init["rho_L"], init["rho_V"],
-                                                            init["W"]), "init_droplets")
+        b.init_droplets(k, init["droplets"], init["rho_L"], init["rho_V"], init["W"])
     b.step(3, 3)
     for k in [0, 1, 7, 64, 100, 128, 200, 255]:
         p, init = runs[k]
