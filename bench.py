@@ -144,16 +144,50 @@ def bench_batch(storage, steps=40, graph_steps=10):
     b.close()
     del b
     torch.cuda.empty_cache()
+    out["mlups_one_launch_per_run"] = round(per_run_launches(cfgs, runs, steps // 4), 1)
     return out
+
+
+def per_run_launches(cfgs, runs, steps):
+    """The same runs as separate lattices, one launch per run per step."""
+    import torch
+
+    from paper_1805_08643_amd.binding import Lattice
+    lats = []
+    for c, (_, init) in zip(cfgs, runs):
+        lat = Lattice(c)
+        lat.init_droplets(init["droplets"], init["rho_L"], init["rho_V"], init["W"])
+        lats.append(lat)
+    N = sum(lat.N for lat in lats)
+    for lat in lats:
+        lat.step(2)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        for lat in lats:
+            lat.step(1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    for lat in lats:
+        lat.close()
+    del lats
+    torch.cuda.empty_cache()
+    return N / (ms * 1e-3) / 1e6
 
 
 def read_traffic(storage, op):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it covers this kernel; None otherwise."""
+    it covers this kernel built from the current sources; None otherwise."""
+    from paper_1805_08643_amd.build import source_digest
     path = os.path.join(ROOT, "profiles", f"step_{WORKLOAD}_{storage}_{op}_pmc.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
+    d = re.search(r"kernel_source_digest:\s*([0-9a-f]+)", txt)
+    if not d or d.group(1) != source_digest():
+        return None
     m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     return float(m.group(1)) if m else None
 
@@ -179,9 +213,19 @@ def cpu_baseline(cfg, init, budget_s):
     steps = extra if extra else 1
     sec = dt if extra else dt1
     assert np.isfinite(f).all()
+    # one thread on a 64^3 crop of the same workload, for scale
+    c1 = dict(cfg, nx=64, ny=64, nz=64)
+    p1 = ref.make_params(c1, nthreads=1)
+    rho1, u1 = li.init_fields(c1, dict(init, droplets=[dict(d, center=(32.0, 32.0, 32.0), r0=12.0)
+                                                         for d in init["droplets"][:1]]))
+    f1 = ref.equilibrium(p1, rho1, u1)
+    t0 = time.perf_counter()
+    f1 = ref.step(p1, f1, 2)
+    st1 = rho1.size * 2 / (time.perf_counter() - t0) / 1e6
     return {"value": N * steps / sec / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": f"full {cfg['nx']}x{cfg['ny']}x{cfg['nz']} lattice, FP64 dense-matrix oracle, "
-                      f"{steps} step(s) after 1 untimed step"}
+                      f"{steps} step(s) after 1 untimed step",
+            "single_thread_mlups": round(st1, 3), "single_thread_sample": "64^3 droplet, 2 steps, 1 thread"}
 
 
 def main():

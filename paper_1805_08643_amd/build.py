@@ -33,6 +33,18 @@ def flags(extra=()):
             "-ffp-contract=fast", "-munsafe-fp-atomics", "-Wall", *extra]
 
 
+def source_digest() -> str:
+    """SHA-256 (first 16 hex digits) over the kernel sources and the compiler
+    flags: identifies the code that a stored profile measured."""
+    import hashlib
+    h = hashlib.sha256()
+    for d in DEPS:
+        with open(d, "rb") as fh:
+            h.update(fh.read())
+    h.update(" ".join(flags()).encode())
+    return h.hexdigest()[:16]
+
+
 def build(force: bool = True, extra=(), out: str | None = None) -> str:
     out = out or LIB
     if not force and os.path.exists(out) and all(os.path.getmtime(out) >= os.path.getmtime(d) for d in DEPS):
