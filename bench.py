@@ -40,24 +40,30 @@ def parse():
     return ap.parse_args()
 
 
-def copy_probe():
+def copy_probe(reps=5, quiet=False):
     """A plain device-to-device copy of known size: 1 GiB read + 1 GiB written
-    per launch, used to scale the HBM byte counters of rocprofv3."""
+    per launch, used to scale the HBM byte counters of rocprofv3 and as the
+    practical read+write rate of the part."""
     import torch
     n = 1 << 28  # float32 elements = 1 GiB
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
+    dst.copy_(src)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    for _ in range(5):
+    for _ in range(reps):
         dst.copy_(src)
     e1.record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / 5
-    print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
-                      "ms_per_copy": round(ms, 4), "GBps_read_plus_write": round(8 * n / (ms * 1e-3) / 1e9, 1)}),
-          flush=True)
+    ms = e0.elapsed_time(e1) / reps
+    out = {"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
+           "ms_per_copy": round(ms, 4), "GBps_read_plus_write": round(8 * n / (ms * 1e-3) / 1e9, 1)}
+    del src, dst
+    torch.cuda.empty_cache()
+    if not quiet:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def make_lattice(storage, op):
@@ -286,6 +292,9 @@ def main():
             torch.cuda.empty_cache()
         out["variants_mlups"] = var
         out["batch"] = {st: bench_batch(st) for st in ("f32", "f16s")}
+    cp = copy_probe(reps=10, quiet=True)
+    out["roofline"]["copy_probe_GBps"] = cp["GBps_read_plus_write"]
+    out["roofline"]["frac_of_copy_probe"] = round(achieved / cp["GBps_read_plus_write"], 4)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, init, a.cpu_seconds)
     print(json.dumps(out), flush=True)
