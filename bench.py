@@ -32,6 +32,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16s", "f64"])
     ap.add_argument("--op", default="nonorth", choices=["nonorth", "orth"])
+    ap.add_argument("--mode", default=None, choices=["fused", "pairs"],
+                    help="step kernel; default: the faster one measured for the storage")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -66,16 +68,19 @@ def copy_probe(reps=5, quiet=False):
     return out
 
 
-def make_lattice(storage, op):
+def make_lattice(storage, op, mode=None):
     import lbm_inputs as li
     from paper_1805_08643_amd import tuning
     from paper_1805_08643_amd.binding import Lattice, f16_exp_for
     cfg, init = li.c3_two_droplets(op=op)
     cfg = dict(cfg, storage=storage, rho_ref=init["rho_V"], f16_exp=f16_exp_for(1.25 * init["rho_L"]))
     lat = Lattice(cfg, "cuda:0")
-    tile = tuning.tile_for(WORKLOAD, storage)
+    mode = mode or tuning.mode_for(WORKLOAD, storage)
+    lat.set_step_mode(mode)
+    tile = tuning.tile_for(WORKLOAD, storage, mode)
     if tile:
         lat.set_tile(*tile)
+    lat.mode = mode
     lat.init_droplets(init["droplets"], init["rho_L"], init["rho_V"], init["W"])
     return lat, cfg, init
 
@@ -183,11 +188,12 @@ def per_run_launches(cfgs, runs, steps):
     return N / (ms * 1e-3) / 1e6
 
 
-def read_traffic(storage, op):
+def read_traffic(storage, op, mode):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it covers this kernel built from the current sources; None otherwise."""
     from paper_1805_08643_amd.build import source_digest
-    path = os.path.join(ROOT, "profiles", f"step_{WORKLOAD}_{storage}_{op}_pmc.md")
+    kern = "step2" if mode == "pairs" else "step"
+    path = os.path.join(ROOT, "profiles", f"{kern}_{WORKLOAD}_{storage}_{op}_pmc.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -249,7 +255,8 @@ def main():
         return
     from paper_1805_08643_amd.binding import algorithmic_bytes_per_node
 
-    lat, cfg, init = make_lattice(a.storage, a.op)
+    lat, cfg, init = make_lattice(a.storage, a.op, a.mode)
+    mode = lat.mode
     N = cfg["nx"] * cfg["ny"] * cfg["nz"]
     ms, wall, kms = time_steps(lat, a.steps, a.warmup, kernel_timing=True)
     diag = lat.diagnostics()
@@ -261,7 +268,7 @@ def main():
     mlups = N / (ms_step * 1e-3) / 1e6
     bpn = algorithmic_bytes_per_node(a.storage)
     achieved = bpn * N / (kms * 1e-3) / 1e9
-    traffic = read_traffic(a.storage, a.op)
+    traffic = read_traffic(a.storage, a.op, mode)
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 5),
@@ -269,24 +276,26 @@ def main():
         "dtype": "f64" if a.storage == "f64" else "f32", "data": "synthetic",
         "config": {"workload": f"{WORKLOAD}: 256^3 periodic, two droplets r0=30 approaching at 0.05, "
                                f"C-S T=0.6Tc a=0.25, sigma=0.105",
-                   "storage": a.storage, "op": a.op, "nodes": N, "tile": list(tile)},
+                   "storage": a.storage, "op": a.op, "nodes": N, "tile": list(tile), "step_mode": mode},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                     "kernel": "k_step (fused psi/force + collide + pull-stream)",
+                     "kernel": ("k_step2 (fused psi/force + collide + pull-stream, two nodes per thread)"
+                                if mode == "pairs" else "k_step (fused psi/force + collide + pull-stream)"),
                      "kernel_ms": round(kms, 5), "algorithmic_bytes_per_node": bpn},
         "mass": diag["mass"], "nonfinite": diag["nonfinite"],
     }
     if not a.no_variants:
         var = {}
-        for st, op in [("f16s", "nonorth"), ("f32", "orth"), ("f64", "nonorth"), ("f32", "nonorth")]:
-            if (st, op) == (a.storage, a.op):
-                var[f"{st}_{op}"] = round(mlups, 1)
+        for st, op, md in [("f32", "nonorth", "fused"), ("f32", "nonorth", "pairs"), ("f16s", "nonorth", "fused"),
+                           ("f16s", "nonorth", "pairs"), ("f32", "orth", None), ("f64", "nonorth", "fused")]:
+            key = f"{st}_{op}_{md or 'default'}"
+            if (st, op) == (a.storage, a.op) and md in (None, mode):
+                var[key] = round(mlups, 1)
                 continue
-            l2, c2, _ = make_lattice(st, op)
+            l2, c2, _ = make_lattice(st, op, md)
             m2, _, k2 = time_steps(l2, max(50, a.steps // 4), 10, kernel_timing=True)
-            var[f"{st}_{op}"] = round(N / (m2 / max(50, a.steps // 4) * 1e-3) / 1e6, 1)
-            var[f"{st}_{op}_hbm_frac"] = round(algorithmic_bytes_per_node(st) * N / (k2 * 1e-3) / 1e9
-                                               / PEAK_HBM_GBS, 4)
+            var[key] = round(N / (m2 / max(50, a.steps // 4) * 1e-3) / 1e6, 1)
+            var[f"{key}_hbm_frac"] = round(algorithmic_bytes_per_node(st) * N / (k2 * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
             l2.close()
             del l2
             torch.cuda.empty_cache()

@@ -189,9 +189,19 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t trials, lbm_tile *best);
  * marching in z with psi and its halo in LDS.  LBM_STEP_SLABS: per z-slab of
  * slab_planes planes, a psi pass then a collide pass that re-reads the slab
  * (sized to stay in the last-level cache) and reads psi from a global array.
- * Both give the same populations bit for bit. */
-enum { LBM_STEP_FUSED = 0, LBM_STEP_SLABS = 1 };
+ * LBM_STEP_PAIRS: the fused kernel with two x-adjacent nodes per thread and
+ * one wide access per direction for both; FP32 and F16S storage with even nx
+ * only (else LBM_ERR_UNSUPPORTED), and the tile's tx must be even (set_tile
+ * and this call return LBM_ERR_INVALID_ARG otherwise).  slab_planes is used
+ * by LBM_STEP_SLABS only but must be >= 1.  All modes give the same
+ * populations bit for bit.  A new context uses LBM_STEP_PAIRS with a
+ * 128 x 8 (or narrower) tile where that mode applies and LBM_STEP_FUSED
+ * otherwise.  Switching to LBM_STEP_PAIRS with an odd tile width replaces
+ * the tile by that default. */
+enum { LBM_STEP_FUSED = 0, LBM_STEP_SLABS = 1, LBM_STEP_PAIRS = 2 };
 lbm_status lbm_set_step_mode(lbm_ctx *ctx, int32_t mode, int32_t slab_planes);
+/* Current step mode and slab size (slab_planes may be NULL). */
+lbm_status lbm_get_step_mode(const lbm_ctx *ctx, int32_t *mode, int32_t *slab_planes);
 
 /* Average device time of one step's kernels (fused mode: the step kernel;
  * slab mode: the psi and collide passes of all slabs) over the steps launched

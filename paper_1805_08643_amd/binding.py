@@ -22,6 +22,7 @@ Q = 19
 OP = {"nonorth": 0, "orth": 1}
 STORAGE = {"f64": 0, "f32": 1, "f16s": 2}
 PSI = {"sqrt_cs": 0, "exp": 1}
+STEP_MODES = {"fused": 0, "slabs": 1, "pairs": 2}
 
 
 class LbmParams(ctypes.Structure):
@@ -93,6 +94,7 @@ SIGNATURES = {
     "lbm_get_tile": (_i32, [_vp, _P(LbmTile)]),
     "lbm_autotune": (_i32, [_vp, _i32, _P(LbmTile)]),
     "lbm_set_step_mode": (_i32, [_vp, _i32, _i32]),
+    "lbm_get_step_mode": (_i32, [_vp, _P(_i32), _P(_i32)]),
     "lbm_set_timing": (_i32, [_vp, _i32]),
     "lbm_kernel_time": (_i32, [_vp, _dp, _P(_i64)]),
     "lbm_step_count": (_i64, [_vp]),
@@ -232,6 +234,12 @@ def lbm_autotune(ctx, trials):
 
 def lbm_set_step_mode(ctx, mode, slab_planes):
     _call("lbm_set_step_mode", _vp(ctx), int(mode), int(slab_planes))
+
+
+def lbm_get_step_mode(ctx):
+    m, sl = _i32(0), _i32(0)
+    _call("lbm_get_step_mode", _vp(ctx), ctypes.byref(m), ctypes.byref(sl))
+    return m.value, sl.value
 
 
 def lbm_set_timing(ctx, enable):
@@ -412,8 +420,13 @@ class Lattice:
         return lbm_autotune(self.ctx, trials)
 
     def set_step_mode(self, mode, slab_planes=32):
-        """mode: "fused" or "slabs"."""
-        lbm_set_step_mode(self.ctx, {"fused": 0, "slabs": 1}[mode], slab_planes)
+        """mode: "fused", "slabs" or "pairs"."""
+        lbm_set_step_mode(self.ctx, STEP_MODES[mode], slab_planes)
+        return self
+
+    def step_mode(self):
+        m, _ = lbm_get_step_mode(self.ctx)
+        return {v: k for k, v in STEP_MODES.items()}[m]
 
     def set_timing(self, on=True):
         lbm_set_timing(self.ctx, on)

@@ -146,18 +146,21 @@ Layout layout_of(const lbm_params &p) {
     return L;
 }
 
-int block_threads(int tx, int ty) {
+// Threads of a step block: one per interior column (two columns per thread
+// in pair mode), and at least one per halo-ring node.
+int block_threads(int tx, int ty, bool pairs = false) {
     const int nh = 2 * (tx + 2) + 2 * ty;
-    const int n = std::max(tx * ty, nh);
+    const int n = std::max(pairs ? (tx / 2) * ty : tx * ty, nh);
     return (n + 63) / 64 * 64;
 }
 
 constexpr size_t kMaxStepLds = 65536;
 
-lbm_status check_tile(const lbm_tile &t, int storage) {
+lbm_status check_tile(const lbm_tile &t, int storage, bool pairs = false) {
     if (t.tx < 1 || t.ty < 1 || t.cz < 1) return fail(LBM_ERR_INVALID_ARG, "tile dims must be positive");
     if (t.tx > 1024 || t.ty > 1024) return fail(LBM_ERR_INVALID_ARG, "tile dims must be <= 1024");
-    if (t.tx * t.ty > STEP_MAX_THREADS || block_threads(t.tx, t.ty) > STEP_MAX_THREADS)
+    if (pairs && t.tx % 2) return fail(LBM_ERR_INVALID_ARG, "pair mode needs an even tile width, got %d", t.tx);
+    if ((pairs ? t.tx / 2 : t.tx) * t.ty > STEP_MAX_THREADS || block_threads(t.tx, t.ty, pairs) > STEP_MAX_THREADS)
         return fail(LBM_ERR_INVALID_ARG, "tile %d x %d needs more than %d threads", t.tx, t.ty, STEP_MAX_THREADS);
     if (4 * (size_t)(t.ty + 2) * (t.tx + 2) * real_bytes(storage) > kMaxStepLds)
         return fail(LBM_ERR_INVALID_ARG, "tile %d x %d needs more than %zu bytes of LDS", t.tx, t.ty, kMaxStepLds);
@@ -201,6 +204,23 @@ lbm_tile default_tile(int nx, int ny, int nz) {
     t.cz = cz;
     return t;
 }
+
+// Default tile of pair mode: rows of up to 128 columns (64 thread pairs), up
+// to 512 interior threads, and z runs long enough that there are about as
+// many tiles as compute units (measured fastest at 256^3: 128 x 8 x 64).
+lbm_tile pair_tile(int nx, int ny, int nz) {
+    lbm_tile t{};
+    t.tx = std::min(nx, 128);
+    t.tx += t.tx % 2;
+    t.ty = std::max(1, std::min(ny, STEP_MAX_THREADS / std::max(1, t.tx / 2)));
+    while (t.ty > 1 && block_threads(t.tx, t.ty, true) > STEP_MAX_THREADS) --t.ty;
+    const int ncol = ((nx + t.tx - 1) / t.tx) * ((ny + t.ty - 1) / t.ty);
+    const int nzc = std::max(1, (256 + ncol - 1) / ncol);
+    t.cz = std::max(std::min(nz, 8), (nz + nzc - 1) / nzc);
+    return t;
+}
+
+bool pairs_apply(const lbm_params &p) { return p.storage != ST_F64 && p.nx % 2 == 0; }
 
 }  // namespace
 
@@ -280,12 +300,24 @@ size_t step_smem(const lbm_ctx *c, const GridDesc &g) {
     return 4 * (size_t)(g.ty + 2) * (g.tx + 2) * real_bytes(c->p.storage);
 }
 
-lbm_status launch_step(lbm_ctx *c, const GridDesc &g, const void *src, void *dst) {
+lbm_status launch_step(lbm_ctx *c, const GridDesc &g, const void *src, void *dst, bool pairs) {
     return dispatch(c, [&](auto S, auto O, auto W) -> lbm_status {
         using T = typename Storage<S.value>::T;
         using R = typename Storage<S.value>::R;
         const unsigned grid = 8u * (unsigned)g.per_xcd;
-        const int threads = block_threads(g.tx, g.ty);
+        const int threads = block_threads(g.tx, g.ty, pairs);
+        if constexpr (S.value != ST_F64) {
+            if (pairs) {
+                // even nx and tx: checked by lbm_set_step_mode / lbm_set_tile
+                if (g.nx % 2 || g.tx % 2) return fail(LBM_ERR_INVALID_ARG, "pair mode needs even nx and tile width");
+                hipLaunchKernelGGL((k_step2<S.value, O.value, W.value>), dim3(grid), dim3(threads), step_smem(c, g),
+                                   c->stream, (const T *)src, (T *)dst, (const R *)c->gpsi(), g, c->pd);
+                HIP_TRY(hipGetLastError());
+                return LBM_OK;
+            }
+        } else if (pairs) {
+            return fail(LBM_ERR_UNSUPPORTED, "pair mode needs FP32 or F16S storage");
+        }
         hipLaunchKernelGGL((k_step<S.value, O.value, W.value>), dim3(grid), dim3(threads), step_smem(c, g),
                            c->stream, (const T *)src, (T *)dst, (const R *)c->gpsi(), g, c->pd);
         HIP_TRY(hipGetLastError());
@@ -338,7 +370,7 @@ lbm_status one_step(lbm_ctx *c) {
     }
     if (c->mode == LBM_STEP_SLABS) {
         if ((s = launch_slabs(c, c->state(), c->other()))) return s;
-    } else if ((s = launch_step(c, c->g, c->state(), c->other()))) {
+    } else if ((s = launch_step(c, c->g, c->state(), c->other(), c->mode == LBM_STEP_PAIRS))) {
         return s;
     }
     if (c->timing) {
@@ -415,7 +447,12 @@ lbm_status lbm_create(const lbm_params *p, void *dev_ws, size_t ws_bytes, void *
     c->L = L;
     c->ws = static_cast<unsigned char *>(dev_ws);
     c->stream = static_cast<hipStream_t>(hip_stream);
-    c->tile = default_tile(p->nx, p->ny, p->nz);
+    if (pairs_apply(*p)) {
+        c->mode = LBM_STEP_PAIRS;
+        c->tile = pair_tile(p->nx, p->ny, p->nz);
+    } else {
+        c->tile = default_tile(p->nx, p->ny, p->nz);
+    }
     fill_grid(c->g, *p, c->tile);
     *out = c;
     return LBM_OK;
@@ -598,7 +635,7 @@ lbm_status lbm_load_state(lbm_ctx *c, const void *dev_buf, size_t bytes) {
 
 lbm_status lbm_set_tile(lbm_ctx *c, const lbm_tile *t) {
     if (!c || !t) return fail(LBM_ERR_INVALID_ARG, "null argument");
-    lbm_status s = check_tile(*t, c->p.storage);
+    lbm_status s = check_tile(*t, c->p.storage, c->mode == LBM_STEP_PAIRS);
     if (s) return s;
     c->tile = *t;
     c->tile.reserved = 0;
@@ -616,15 +653,18 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t trials, lbm_tile *best) {
     if (!c) return fail(LBM_ERR_INVALID_ARG, "ctx is NULL");
     if (trials < 1) return fail(LBM_ERR_INVALID_ARG, "trials < 1");
     std::vector<lbm_tile> cand;
-    const int txs[] = {16, 32, 64, 128};
+    const bool pairs = c->mode == LBM_STEP_PAIRS;
+    const int txs[] = {16, 32, 64, 128, 256};
     const int tys[] = {1, 2, 4, 8, 16, 32};
     const int czs[] = {4, 8, 16, 32, 64, 128};
+    const int txmax = pairs ? 256 : 128;
     auto add = [&](int tx, int ty, int cz) {
         lbm_tile t{tx, ty, std::min(cz, c->p.nz), 0};
-        if (t.tx > c->p.nx && t.tx != std::min(c->p.nx, 128)) return;
+        if (tx > txmax) return;
+        if (t.tx > c->p.nx && t.tx != std::min(c->p.nx, txmax)) return;
         if (t.ty > c->p.ny) return;
-        if (t.tx * t.ty < 64) return;
-        if (check_tile(t, c->p.storage) != LBM_OK) return;
+        if ((pairs ? t.tx / 2 : t.tx) * t.ty < 64) return;
+        if (check_tile(t, c->p.storage, pairs) != LBM_OK) return;
         for (auto &o : cand)
             if (o.tx == t.tx && o.ty == t.ty && o.cz == t.cz) return;
         cand.push_back(t);
@@ -632,7 +672,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t trials, lbm_tile *best) {
     for (int tx : txs)
         for (int ty : tys)
             for (int cz : czs) add(std::min(tx, c->p.nx), ty, cz);
-    if (cand.empty()) cand.push_back(default_tile(c->p.nx, c->p.ny, c->p.nz));
+    if (cand.empty()) cand.push_back(pairs ? pair_tile(c->p.nx, c->p.ny, c->p.nz) : default_tile(c->p.nx, c->p.ny, c->p.nz));
     g_err.clear();
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
@@ -644,10 +684,10 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t trials, lbm_tile *best) {
     for (const lbm_tile &t : cand) {
         GridDesc g{};
         fill_grid(g, c->p, t);
-        if ((s = launch_step(c, g, c->state(), c->other()))) return s;  // warm-up
+        if ((s = launch_step(c, g, c->state(), c->other(), pairs))) return s;  // warm-up
         HIP_TRY(hipEventRecord(e0, c->stream));
         for (int k = 0; k < trials; ++k)
-            if ((s = launch_step(c, g, c->state(), c->other()))) return s;
+            if ((s = launch_step(c, g, c->state(), c->other(), pairs))) return s;
         HIP_TRY(hipEventRecord(e1, c->stream));
         HIP_TRY(hipEventSynchronize(e1));
         float ms = 0;
@@ -667,10 +707,27 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t trials, lbm_tile *best) {
 
 lbm_status lbm_set_step_mode(lbm_ctx *c, int32_t mode, int32_t slab_planes) {
     if (!c) return fail(LBM_ERR_INVALID_ARG, "ctx is NULL");
-    if (mode != LBM_STEP_FUSED && mode != LBM_STEP_SLABS) return fail(LBM_ERR_INVALID_ARG, "unknown step mode %d", mode);
+    if (mode != LBM_STEP_FUSED && mode != LBM_STEP_SLABS && mode != LBM_STEP_PAIRS)
+        return fail(LBM_ERR_INVALID_ARG, "unknown step mode %d", mode);
     if (slab_planes < 1) return fail(LBM_ERR_INVALID_ARG, "slab_planes < 1");
+    if (mode == LBM_STEP_PAIRS) {
+        if (c->p.storage == ST_F64) return fail(LBM_ERR_UNSUPPORTED, "pair mode needs FP32 or F16S storage");
+        if (c->p.nx % 2) return fail(LBM_ERR_UNSUPPORTED, "pair mode needs an even nx, got %d", c->p.nx);
+        if (check_tile(c->tile, c->p.storage, true) != LBM_OK) {
+            g_err.clear();
+            c->tile = pair_tile(c->p.nx, c->p.ny, c->p.nz);
+            fill_grid(c->g, c->p, c->tile);
+        }
+    }
     c->mode = mode;
     c->slab = slab_planes;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_step_mode(const lbm_ctx *c, int32_t *mode, int32_t *slab_planes) {
+    if (!c || !mode) return fail(LBM_ERR_INVALID_ARG, "null argument");
+    *mode = c->mode;
+    if (slab_planes) *slab_planes = c->slab;
     return LBM_OK;
 }
 

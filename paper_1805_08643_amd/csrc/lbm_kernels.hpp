@@ -347,6 +347,342 @@ __global__ void LBM_STEP_ATTR
 }
 
 // ---------------------------------------------------------------------------
+// Two x-adjacent nodes per thread (FP32 and F16S storage, even nx).
+//
+// A thread owns nodes (xa, xa + 1) with xa even.  For every direction one
+// wide access moves both values: 8 bytes for FP32, 4 for F16S.  Directions
+// with e_x = 0 read an aligned pair; e_x = +1 reads the pair starting at
+// xa - 1 and e_x = -1 the pair starting at xa + 1.  On the periodic seam
+// (xa = 0 for e_x = +1, xa + 1 = nx - 1 for e_x = -1) the shifted pair would
+// wrap: the lane reads the aligned pair instead and fetches the one wrapped
+// value with a narrow load, in a branch only waves holding a seam lane take.
+// The arithmetic per node is that of the one-node kernel, so the two give
+// the same populations bit for bit.
+// ---------------------------------------------------------------------------
+template <int S> struct Wide;
+template <> struct Wide<ST_F32> {
+    using W = unsigned long long;  // two values
+    using B = uint32_t;            // bits of one value
+    __device__ static inline W ld(rsrc_t r, uint32_t vo, uint32_t so) {
+        return __builtin_bit_cast(W, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, LBM_BUF_AUX));
+    }
+    __device__ static inline B one(rsrc_t r, uint32_t vo, uint32_t so) {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, LBM_BUF_AUX);
+    }
+    __device__ static inline B lo(W w) { return (B)w; }
+    __device__ static inline B hi(W w) { return (B)(w >> 32); }
+    __device__ static inline float cvt(B b, float, float) { return __uint_as_float(b); }
+    __device__ static inline void st2(float a, float b, rsrc_t r, uint32_t vo, uint32_t so, float, float) {
+        using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+        const W w = (W)__float_as_uint(a) | ((W)__float_as_uint(b) << 32);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, w), r, (int)vo, (int)so, LBM_BUF_AUX);
+    }
+};
+template <> struct Wide<ST_F16S> {
+    using W = uint32_t;
+    using B = uint16_t;
+    __device__ static inline W ld(rsrc_t r, uint32_t vo, uint32_t so) {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, LBM_BUF_AUX);
+    }
+    __device__ static inline B one(rsrc_t r, uint32_t vo, uint32_t so) {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, LBM_BUF_AUX);
+    }
+    __device__ static inline B lo(W w) { return (B)w; }
+    __device__ static inline B hi(W w) { return (B)(w >> 16); }
+    __device__ static inline float cvt(B b, float shift, float hsi) {
+        return fmaf(__half2float(__ushort_as_half(b)), hsi, shift);
+    }
+    __device__ static inline void st2(float a, float b, rsrc_t r, uint32_t vo, uint32_t so, float shs, float hs) {
+        const uint32_t ha = __half_as_ushort(__float2half_rn(fmaf(a, hs, -shs)));
+        const uint32_t hb = __half_as_ushort(__float2half_rn(fmaf(b, hs, -shs)));
+        __builtin_amdgcn_raw_buffer_store_b32(ha | (hb << 16), r, (int)vo, (int)so, LBM_BUF_AUX);
+    }
+};
+
+// Byte offsets within one z-plane of one direction for a node pair.
+struct NbOff2 {
+    uint32_t c, ym, yp;    // aligned pair at xa, rows y, y-1, y+1
+    uint32_t xm, mm, pm;   // pair from xa - 1 (xa on the seam), rows y, y-1, y+1
+    uint32_t xp, mp, pp;   // pair from xa + 1 (xa on the seam), rows y, y-1, y+1
+    uint32_t ry, rym, ryp; // row starts, for the wrapped value on the seam
+    uint32_t xlast;        // (nx - 1) * sizeof(T)
+    __device__ inline void set(int xa, bool wl, bool wr, int y, int ym_, int yp_, int nx, uint32_t E) {
+        const uint32_t rb = (uint32_t)nx * E;
+        ry = (uint32_t)y * rb;
+        rym = (uint32_t)ym_ * rb;
+        ryp = (uint32_t)yp_ * rb;
+        const uint32_t b0 = (uint32_t)xa * E;
+        const uint32_t bm = (uint32_t)(wl ? xa : xa - 1) * E;
+        const uint32_t bp = (uint32_t)(wr ? xa : xa + 1) * E;
+        c = ry + b0;
+        ym = rym + b0;
+        yp = ryp + b0;
+        xm = ry + bm;
+        mm = rym + bm;
+        pm = ryp + bm;
+        xp = ry + bp;
+        mp = rym + bp;
+        pp = ryp + bp;
+        xlast = (uint32_t)(nx - 1) * E;
+    }
+};
+
+// Pull of a node pair: fa for node xa, fb for node xa + 1.  wl: xa == 0;
+// wr: xa + 1 == nx - 1 (the pair's shifted reads would cross the seam).
+template <int S, bool WALL>
+__device__ inline void pull2(const PopBuf &A, int nz, uint32_t PB, int z, const NbOff2 &o, bool wl, bool wr,
+                             const Phys<typename Storage<S>::R> &P, typename Storage<S>::R fa[Q],
+                             typename Storage<S>::R fb[Q]) {
+    using WD = Wide<S>;
+    using W = typename WD::W;
+    using B = typename WD::B;
+    const bool bot = WALL && z == 0;
+    const bool top = WALL && z == nz - 1;
+    const int zm = WALL ? (bot ? z : z - 1) : (z == 0 ? nz - 1 : z - 1);
+    const int zq = WALL ? (top ? z : z + 1) : (z == nz - 1 ? 0 : z + 1);
+    const uint32_t pc = (uint32_t)z * PB, pm = (uint32_t)zm * PB, pq = (uint32_t)zq * PB;
+    W w[Q];
+#define LBM_LW(i, d, plane, off) w[i] = WD::ld(A.of(d), (off), A.so((d), (plane)))
+    LBM_LW(0, 0, pc, o.c);
+    LBM_LW(1, 1, pc, o.xm);
+    LBM_LW(2, 2, pc, o.xp);
+    LBM_LW(3, 3, pc, o.ym);
+    LBM_LW(4, 4, pc, o.yp);
+    LBM_LW(7, 7, pc, o.mm);
+    LBM_LW(8, 8, pc, o.pp);
+    LBM_LW(9, 9, pc, o.pm);
+    LBM_LW(10, 10, pc, o.mp);
+    if (!bot) {
+        LBM_LW(5, 5, pm, o.c);
+        LBM_LW(11, 11, pm, o.xm);
+        LBM_LW(14, 14, pm, o.xp);
+        LBM_LW(15, 15, pm, o.ym);
+        LBM_LW(18, 18, pm, o.yp);
+    } else {
+        LBM_LW(5, 6, pc, o.c);
+        LBM_LW(11, 12, pc, o.c);
+        LBM_LW(14, 13, pc, o.c);
+        LBM_LW(15, 16, pc, o.c);
+        LBM_LW(18, 17, pc, o.c);
+    }
+    if (!top) {
+        LBM_LW(6, 6, pq, o.c);
+        LBM_LW(12, 12, pq, o.xp);
+        LBM_LW(13, 13, pq, o.xm);
+        LBM_LW(16, 16, pq, o.yp);
+        LBM_LW(17, 17, pq, o.ym);
+    } else {
+        LBM_LW(6, 5, pc, o.c);
+        LBM_LW(12, 11, pc, o.c);
+        LBM_LW(13, 14, pc, o.c);
+        LBM_LW(16, 15, pc, o.c);
+        LBM_LW(17, 18, pc, o.c);
+    }
+#undef LBM_LW
+    // Seam values: e_x = +1 needs x = nx - 1 for node xa = 0; e_x = -1 needs
+    // x = 0 for node xa + 1 = nx - 1.  Order: 1, 7, 9, 11, 13 / 2, 8, 10, 14, 12.
+    B sl[5] = {0, 0, 0, 0, 0}, sr[5] = {0, 0, 0, 0, 0};
+    if (wl) {
+        sl[0] = WD::one(A.of(1), o.ry + o.xlast, A.so(1, pc));
+        sl[1] = WD::one(A.of(7), o.rym + o.xlast, A.so(7, pc));
+        sl[2] = WD::one(A.of(9), o.ryp + o.xlast, A.so(9, pc));
+        if (!bot) sl[3] = WD::one(A.of(11), o.ry + o.xlast, A.so(11, pm));
+        if (!top) sl[4] = WD::one(A.of(13), o.ry + o.xlast, A.so(13, pq));
+    }
+    if (wr) {
+        sr[0] = WD::one(A.of(2), o.ry, A.so(2, pc));
+        sr[1] = WD::one(A.of(8), o.ryp, A.so(8, pc));
+        sr[2] = WD::one(A.of(10), o.rym, A.so(10, pc));
+        if (!bot) sr[3] = WD::one(A.of(14), o.ry, A.so(14, pm));
+        if (!top) sr[4] = WD::one(A.of(12), o.ry, A.so(12, pq));
+    }
+    // Unpack.  On the seam the aligned pair (xa, xa + 1) was read: for e_x =
+    // +1 node xa + 1 takes the value at xa (its low half); for e_x = -1 node
+    // xa takes the value at xa + 1 (its high half).
+    auto plain = [&](int i) {
+        fa[i] = WD::cvt(WD::lo(w[i]), P.sh(i), P.hsi);
+        fb[i] = WD::cvt(WD::hi(w[i]), P.sh(i), P.hsi);
+    };
+    auto from_left = [&](int i, B seam, bool shifted) {  // e_x = +1
+        const B a = wl && shifted ? seam : WD::lo(w[i]);
+        const B b = wl && shifted ? WD::lo(w[i]) : WD::hi(w[i]);
+        fa[i] = WD::cvt(a, P.sh(i), P.hsi);
+        fb[i] = WD::cvt(b, P.sh(i), P.hsi);
+    };
+    auto from_right = [&](int i, B seam, bool shifted) {  // e_x = -1
+        const B a = wr && shifted ? WD::hi(w[i]) : WD::lo(w[i]);
+        const B b = wr && shifted ? seam : WD::hi(w[i]);
+        fa[i] = WD::cvt(a, P.sh(i), P.hsi);
+        fb[i] = WD::cvt(b, P.sh(i), P.hsi);
+    };
+    plain(0);
+    plain(3);
+    plain(4);
+    plain(5);
+    plain(6);
+    plain(15);
+    plain(16);
+    plain(17);
+    plain(18);
+    from_left(1, sl[0], true);
+    from_left(7, sl[1], true);
+    from_left(9, sl[2], true);
+    from_left(11, sl[3], !bot);
+    from_left(13, sl[4], !top);
+    from_right(2, sr[0], true);
+    from_right(8, sr[1], true);
+    from_right(10, sr[2], true);
+    from_right(14, sr[3], !bot);
+    from_right(12, sr[4], !top);
+}
+
+// z-march of a tile with two nodes per thread: tx nodes (even) by ty rows,
+// (tx / 2) * ty interior threads; the halo ring is pulled one node per
+// thread as in tile_march.
+template <int S, int OP, bool WALL>
+__device__ inline void tile_march2(const typename Storage<S>::T *__restrict__ A,
+                                   typename Storage<S>::T *__restrict__ B,
+                                   const typename Storage<S>::R *__restrict__ gpsi, const GridDesc &g,
+                                   const Phys<typename Storage<S>::R> &P, int tile,
+                                   typename Storage<S>::R *ps) {
+    using ST = Storage<S>;
+    using R = typename ST::R;
+    using WD = Wide<S>;
+    const int TX = g.tx, TY = g.ty, TXP = g.tx >> 1;
+    const int SX = TX + 2, SP = (TY + 2) * SX;
+    int t = tile;
+    const int itx = t % g.ntx;
+    t /= g.ntx;
+    const int ity = t % g.nty;
+    const int izc = t / g.nty;
+    const int x0 = itx * TX, y0 = ity * TY;
+    const int zb = izc * g.cz;
+    const int ze = min(zb + g.cz, g.nz);
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const size_t N = (size_t)g.N;
+    const int tid = threadIdx.x;
+
+    // Interior pair of this thread: nodes x0 + 2 lx and x0 + 2 lx + 1.  A
+    // pair starting at nx (a ragged last tile) supplies psi of the wrapped
+    // columns 0 and 1 to the last real column.
+    const int lx = tid % TXP, ly = tid / TXP;
+    const bool inner = ly < TY;
+    const int xa = x0 + 2 * lx;
+    const bool need_in = inner && xa <= nx && ly <= ny - y0;
+    const bool active = inner && xa < nx && y0 + ly < ny;
+    const int gx = xa >= nx ? xa - nx : xa, gy = wrapi(y0 + ly, ny);
+    const bool wl = gx == 0, wr = gx + 1 == nx - 1;
+    const int cin = (ly + 1) * SX + 2 * lx + 1;
+    constexpr uint32_t E = sizeof(typename ST::T);
+    const uint32_t PB = (uint32_t)((size_t)nx * ny * E);
+    PopBuf bA, bB;
+    bA.set(A, N);
+    bB.set(B, N);
+    NbOff2 oin;
+    oin.set(gx, wl, wr, gy, wrapi(gy - 1, ny), wrapi(gy + 1, ny), nx, E);
+
+    const int nh = 2 * SX + 2 * TY;
+    int hlx = -1, hly = -1;
+    bool halo = false;
+    if (tid < nh) {
+        int h = tid;
+        if (h < SX) {
+            hlx = h - 1;
+            hly = -1;
+        } else if (h < 2 * SX) {
+            hlx = h - SX - 1;
+            hly = TY;
+        } else if (h < 2 * SX + TY) {
+            hlx = -1;
+            hly = h - 2 * SX;
+        } else {
+            hlx = TX;
+            hly = h - 2 * SX - TY;
+        }
+        halo = hlx <= nx - x0 && hly <= ny - y0;
+    }
+    const int hx = wrapi(x0 + hlx, nx), hy = wrapi(y0 + hly, ny);
+    const int chl = (hly + 1) * SX + hlx + 1;
+    NbOff oh;
+    oh.set(hx, wrapi(hx - 1, nx), wrapi(hx + 1, nx), hy, wrapi(hy - 1, ny), wrapi(hy + 1, ny), nx, E);
+
+    R ca[Q], cb[Q], na[Q], nb[Q], fh[Q];
+    R rca = (R)1, rcb = (R)1, rna = (R)1, rnb = (R)1;
+
+    auto issue = [&](int zp, R *fa, R *fb) {
+        if (WALL && (zp < 0 || zp >= nz)) return;
+        const int zw = WALL ? zp : wrapi(zp, nz);
+        if (need_in) pull2<S, WALL>(bA, nz, PB, zw, oin, wl, wr, P, fa, fb);
+        if (halo) pull<S, WALL>(bA, nz, PB, zw, oh, P, fh);
+    };
+    auto finish = [&](int zp, R *slot, const R *fa, const R *fb, R &ra, R &rb) {
+        if (WALL && (zp < 0 || zp >= nz)) {
+            const R *gp = gpsi + (zp < 0 ? 0 : (size_t)nx * ny);
+            if (need_in) {
+                slot[cin] = gp[(size_t)gy * nx + gx];
+                slot[cin + 1] = gp[(size_t)gy * nx + gx + 1];
+            }
+            if (halo) slot[chl] = gp[(size_t)hy * nx + hx];
+            return;
+        }
+        if (need_in) {
+            ra = sum19<R>(fa);
+            rb = sum19<R>(fb);
+            slot[cin] = pseudo_psi<R>(P, ra);
+            slot[cin + 1] = pseudo_psi<R>(P, rb);
+        }
+        if (halo) slot[chl] = pseudo_psi<R>(P, sum19<R>(fh));
+    };
+    auto slot_of = [&](int z) { return ps + ((z - zb + 1) & 3) * SP; };
+
+    issue(zb - 1, na, nb);
+    finish(zb - 1, slot_of(zb - 1), na, nb, rna, rnb);
+    issue(zb, ca, cb);
+    finish(zb, slot_of(zb), ca, cb, rca, rcb);
+    for (int z = zb; z < ze; ++z) {
+        issue(z + 1, na, nb);
+        finish(z + 1, slot_of(z + 1), na, nb, rna, rnb);
+        lds_barrier();
+        if (active) {
+            const R *lo = slot_of(z - 1), *mid = slot_of(z), *hi = slot_of(z + 1);
+            R ax, ay, az;
+            psi_stencil<R>(lo, mid, hi, cin, SX, ax, ay, az);
+            R mG_psi = -P.G * mid[cin];
+            collide<R, OP>(ca, rca, mG_psi * ax + rca * P.gx, mG_psi * ay + rca * P.gy, mG_psi * az + rca * P.gz,
+                           ax * ax + ay * ay + az * az, P);
+            psi_stencil<R>(lo, mid, hi, cin + 1, SX, ax, ay, az);
+            mG_psi = -P.G * mid[cin + 1];
+            collide<R, OP>(cb, rcb, mG_psi * ax + rcb * P.gx, mG_psi * ay + rcb * P.gy, mG_psi * az + rcb * P.gz,
+                           ax * ax + ay * ay + az * az, P);
+            const uint32_t pz = (uint32_t)z * PB;
+#pragma unroll
+            for (int a = 0; a < Q; ++a) WD::st2(ca[a], cb[a], bB.of(a), oin.c, bB.so(a, pz), P.shh(a), P.hs);
+        }
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            ca[a] = na[a];
+            cb[a] = nb[a];
+        }
+        rca = rna;
+        rcb = rnb;
+    }
+}
+
+template <int S, int OP, bool WALL>
+__global__ void LBM_STEP_ATTR
+    k_step2(const typename Storage<S>::T *__restrict__ A, typename Storage<S>::T *__restrict__ B,
+            const typename Storage<S>::R *__restrict__ gpsi, GridDesc g, PhysD pd) {
+    using R = typename Storage<S>::R;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    R *ps = reinterpret_cast<R *>(smem_raw);
+    const int tile = xcd_tile(blockIdx.x, g.per_xcd);
+    if (tile >= g.ntiles) return;
+    Phys<R> P;
+    P.load(pd);
+    tile_march2<S, OP, WALL>(A, B, gpsi, g, P, tile, ps);
+}
+
+// ---------------------------------------------------------------------------
 // Batched independent periodic runs.  One persistent launch per time step:
 // every block walks a work list of (run, tile) items; item -> run by binary
 // search over the runs' first-item indices.  Items are dealt so that each

@@ -1,18 +1,37 @@
-"""Launch shapes (tx, ty, cz) of the fused step for the standard workloads,
-picked by ``lbm_autotune`` on an MI355X.  Any shape is correct; these are
-the measured fastest."""
+"""Launch shapes (tx, ty, cz) and step kernels for the standard workloads,
+measured fastest on an MI355X (``lbm_autotune`` and sweeps).  Any shape and
+either kernel give the same populations; these are the fastest found."""
 
 STEP_TILES = {
-    # (workload, storage) -> (tx, ty, cz)
-    ("droplet_32", "f64"): (32, 8, 8),
-    ("laplace_128", "f64"): (64, 4, 16),
-    ("laplace_128", "f32"): (64, 4, 16),
-    ("two_droplets_256", "f64"): (128, 4, 64),
-    ("two_droplets_256", "f32"): (64, 4, 32),
-    ("two_droplets_256", "f16s"): (64, 4, 32),
-    ("sessile_384x384x192", "f32"): (64, 4, 32),
+    # (workload, storage, mode) -> (tx, ty, cz); mode "fused": one node per
+    # thread, "pairs": two x-adjacent nodes per thread (tx counts nodes)
+    ("droplet_32", "f64", "fused"): (32, 8, 8),
+    ("laplace_128", "f64", "fused"): (64, 4, 16),
+    ("laplace_128", "f32", "fused"): (64, 4, 16),
+    ("laplace_128", "f32", "pairs"): (64, 8, 8),
+    ("laplace_128", "f16s", "fused"): (64, 8, 16),
+    ("laplace_128", "f16s", "pairs"): (64, 8, 8),
+    ("two_droplets_256", "f64", "fused"): (128, 4, 64),
+    ("two_droplets_256", "f32", "fused"): (64, 4, 128),
+    ("two_droplets_256", "f32", "pairs"): (128, 8, 64),
+    ("two_droplets_256", "f16s", "fused"): (64, 4, 32),
+    ("two_droplets_256", "f16s", "pairs"): (128, 8, 64),
+    ("sessile_384x384x192", "f32", "fused"): (64, 4, 32),
+    ("sessile_384x384x192", "f32", "pairs"): (128, 8, 16),
+}
+
+# Faster step kernel per (workload, storage); absent: "fused".
+STEP_MODES = {
+    ("laplace_128", "f16s"): "pairs",
+    ("two_droplets_256", "f32"): "pairs",
+    ("two_droplets_256", "f16s"): "pairs",
+    ("sessile_384x384x192", "f32"): "pairs",
 }
 
 
-def tile_for(workload: str, storage: str):
-    return STEP_TILES.get((workload, storage))
+def mode_for(workload: str, storage: str) -> str:
+    return STEP_MODES.get((workload, storage), "fused")
+
+
+def tile_for(workload: str, storage: str, mode: str = "fused"):
+    return STEP_TILES.get((workload, storage, mode))

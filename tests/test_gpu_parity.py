@@ -27,7 +27,7 @@ from scipy.ndimage import maximum_filter
 
 import lbm_inputs as li
 from oracle import ref
-from paper_1805_08643_amd import tuning
+from paper_1805_08643_amd import binding, tuning
 from paper_1805_08643_amd.binding import Lattice, f16_exp_for
 
 pytestmark = pytest.mark.gpu
@@ -40,11 +40,15 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def gpu_states(cfg, rho, u, checkpoints, tile=None):
+def gpu_states(cfg, rho, u, checkpoints, tile=None, mode=None):
+    """States after each checkpoint; mode None keeps the library's default
+    step kernel (two nodes per thread for FP32/F16S with even nx)."""
     _need_gpu()
     print(f"[gpu] {cfg['nx']}x{cfg['ny']}x{cfg['nz']} op={cfg.get('op')} storage={cfg.get('storage')} "
-          f"wall={cfg.get('wall_z', 0)} tile={tile} steps={checkpoints}", flush=True)
+          f"wall={cfg.get('wall_z', 0)} tile={tile} mode={mode} steps={checkpoints}", flush=True)
     lat = Lattice(cfg)
+    if mode is not None:
+        lat.set_step_mode(mode)
     if tile is not None:
         lat.set_tile(*tile)
     lat.init_fields(rho, u)
@@ -145,12 +149,13 @@ def test_fp64_parity_500_steps_droplet_32():
         assert e < 1e-12, (s, e)
 
 
+@pytest.mark.parametrize("mode", ["fused", "pairs"])
 @pytest.mark.parametrize("op", ["nonorth", "orth"])
 @pytest.mark.parametrize("name", ["droplet_32", "ragged_70x37x21", "walls_40x33x19_60deg"])
-def test_fp32_parity(name, op):
+def test_fp32_parity(name, op, mode):
     cfg, rho, u, tile = _case(name, op, "f32")
     cps = [1, 10]
-    got = gpu_states(cfg, rho, u, cps, tile)
+    got = gpu_states(cfg, rho, u, cps, tile, mode)
     want = oracle_states(cfg, rho, u, cps)
     for s, g, w in zip(cps, got, want):
         e = rho_err(g, w)
@@ -158,11 +163,12 @@ def test_fp32_parity(name, op):
         assert e < 5e-6 * s, (s, e)
 
 
+@pytest.mark.parametrize("mode", ["fused", "pairs"])
 @pytest.mark.parametrize("name", ["droplet_32", "ragged_70x37x21", "walls_40x33x19_60deg"])
-def test_f16s_parity(name):
+def test_f16s_parity(name, mode):
     cfg, rho, u, tile = _case(name, "nonorth", "f16s")
     cps = [1, 10]
-    got = gpu_states(cfg, rho, u, cps, tile)
+    got = gpu_states(cfg, rho, u, cps, tile, mode)
     want = oracle_states(cfg, rho, u, [0] + cps)
     f0, want = want[0], want[1:]
     for s, g, w in zip(cps, got, want):
@@ -195,13 +201,16 @@ def test_f16_storage_format_round_trip():
     assert np.array_equal(got, want)
 
 
-def test_tiles_give_bit_identical_results():
+@pytest.mark.parametrize("mode", ["fused", "pairs"])
+def test_tiles_give_bit_identical_results(mode):
     """Every node's arithmetic is independent of the tiling, so any tile
     shape (including ragged tails) must give the same bits."""
     cfg, rho, u, _ = _case("ragged_70x37x21", "nonorth", "f32")
     ref_state = None
-    for tile in [(32, 8, 8), (64, 4, 21), (16, 16, 3), (70, 4, 5), (8, 32, 1)]:
-        s = gpu_states(cfg, rho, u, [3], tile)[0]
+    for tile in [(32, 8, 8), (64, 4, 21), (16, 16, 3), (70, 4, 5), (8, 32, 1), (128, 8, 21)]:
+        if mode == "fused" and tile[0] * tile[1] > 512:
+            continue
+        s = gpu_states(cfg, rho, u, [3], tile, mode)[0]
         if ref_state is None:
             ref_state = s
         else:
@@ -215,13 +224,79 @@ def test_slab_mode_bit_identical_to_fused(name, storage, slab):
     """The two-pass slab step computes every node with the same arithmetic as
     the fused kernel, so the populations agree bit for bit."""
     cfg, rho, u, tile = _case(name, "nonorth", storage)
-    fused = gpu_states(cfg, rho, u, [3], tile)[0]
+    fused = gpu_states(cfg, rho, u, [3], tile, "fused")[0]
     lat = Lattice(cfg)
     lat.set_step_mode("slabs", slab)
     lat.init_fields(rho, u).step(3)
     got = lat.read_populations().cpu().numpy()
     lat.close()
     assert np.array_equal(got, fused)
+
+
+PAIR_CASES = [("ragged_70x37x21", "f32", (64, 8, 5)), ("ragged_70x37x21", "f16s", (32, 4, 7)),
+              ("walls_40x33x19_60deg", "f32", (16, 8, 7)), ("walls_40x33x19_60deg", "f16s", (40, 2, 19)),
+              ("droplet_32", "f32", (2, 16, 4)), ("droplet_32", "f16s", (32, 8, 8))]
+
+
+@pytest.mark.parametrize("op", ["nonorth", "orth"])
+@pytest.mark.parametrize("name,storage,tile", PAIR_CASES)
+def test_pair_mode_bit_identical_to_fused(name, storage, tile, op):
+    """Two nodes per thread with wide accesses: same arithmetic per node as
+    the one-node kernel, so the same populations bit for bit.  The tiles
+    cover ragged last tiles in x and y (a pair starting at nx supplies the
+    wrapped columns), seam lanes at both ends of x, and walls."""
+    cfg, rho, u, ftile = _case(name, op, storage)
+    fused = gpu_states(cfg, rho, u, [3], ftile, "fused")[0]
+    print(f"[gpu] pairs {name} {storage} {op} tile={tile}", flush=True)
+    lat = Lattice(cfg)
+    lat.set_step_mode("pairs").set_tile(*tile)
+    lat.init_fields(rho, u).step(3)
+    got = lat.read_populations().cpu().numpy()
+    lat.close()
+    assert np.array_equal(got, fused)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16s"])
+def test_pair_mode_two_column_lattice(storage):
+    """nx = 2: one pair per row, on the seam at both ends."""
+    cfg = li.params(2, 6, 5, T_over_Tc=0.8, storage=storage, rho_ref=0.02, f16_exp=f16_exp_for(0.4))
+    rho, u = li.random_fields(2, 6, 5, seed=11)
+    fused = gpu_states(cfg, rho, u, [2], (2, 6, 5), "fused")[0]
+    lat = Lattice(cfg)
+    lat.set_step_mode("pairs").set_tile(2, 6, 5)
+    lat.init_fields(rho, u).step(2)
+    got = lat.read_populations().cpu().numpy()
+    lat.close()
+    assert np.array_equal(got, fused)
+
+
+def test_default_step_mode():
+    _need_gpu()
+    for shape, storage, want in [((32, 8, 8), "f32", "pairs"), ((32, 8, 8), "f16s", "pairs"),
+                                 ((32, 8, 8), "f64", "fused"), ((33, 8, 8), "f32", "fused")]:
+        lat = Lattice(li.params(*shape, storage=storage))
+        assert lat.step_mode() == want, (shape, storage)
+        lat.close()
+
+
+def test_pair_mode_rejections():
+    _need_gpu()
+    lat = Lattice(li.params(32, 8, 8, storage="f64"))
+    with pytest.raises(binding.LbmError) as e:
+        lat.set_step_mode("pairs")
+    assert e.value.status == -5
+    lat.close()
+    lat = Lattice(li.params(33, 8, 8, storage="f32"))
+    with pytest.raises(binding.LbmError) as e:
+        lat.set_step_mode("pairs")
+    assert e.value.status == -5
+    lat.close()
+    lat = Lattice(li.params(32, 8, 8, storage="f32"))
+    lat.set_step_mode("pairs")
+    with pytest.raises(binding.LbmError) as e:
+        lat.set_tile(15, 4, 4)
+    assert e.value.status == -1
+    lat.close()
 
 
 def test_init_droplets_on_device_matches_generator():
@@ -360,9 +435,11 @@ def test_full_size_sampled_parity(workload, storage):
                                     np.flatnonzero(np.abs(rho - 0.5 * (init["rho_L"] + init["rho_V"]))
                                                    < 0.25 * (init["rho_L"] - init["rho_V"]))[::97][:2000],
                                     [0, N - 1]]))
-    tile = tuning.tile_for(workload, storage)
-    print(f"[gpu] {workload} {storage} tile={tile} samples={idx.size}", flush=True)
+    mode = tuning.mode_for(workload, storage)
+    tile = tuning.tile_for(workload, storage, mode)
+    print(f"[gpu] {workload} {storage} mode={mode} tile={tile} samples={idx.size}", flush=True)
     lat = Lattice(cfg)
+    lat.set_step_mode(mode)
     if tile:
         lat.set_tile(*tile)
     lat.init_fields(rho, u).step(1)
