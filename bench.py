@@ -139,7 +139,7 @@ def bench_batch(storage, steps=40, graph_steps=10):
         kms, _ = b.kernel_time()
         return ms, kms
 
-    out = {"runs": len(runs), "nodes": N, "storage": storage}
+    out = {"runs": len(runs), "nodes": N, "storage": storage, "step_mode": b.step_mode()}
     ms, _ = timed(0)
     out["mlups_plain_launches"] = round(N / (ms * 1e-3) / 1e6, 1)
     ms, _ = timed(graph_steps)
@@ -148,6 +148,7 @@ def bench_batch(storage, steps=40, graph_steps=10):
     ms, kms = timed(graph_steps)
     out["mlups_tuned_graph"] = round(N / (ms * 1e-3) / 1e6, 1)
     out["tuned_blocks"] = blocks
+    out["tuned_step_mode"] = b.step_mode()
     out["ms_per_step"] = round(ms, 4)
     out["hbm_frac"] = round(algorithmic_bytes_per_node(storage) * N / (kms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
     d = b.read_fields(0)["rho"]

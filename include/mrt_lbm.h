@@ -231,10 +231,18 @@ lbm_status lbm_batch_init_fields(lbm_batch *b, int32_t run, const double *rho, c
 lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps, int32_t graph_steps);
 lbm_status lbm_batch_read_fields(lbm_batch *b, int32_t run, double *rho, double *u, double *p);
 lbm_status lbm_batch_read_populations(lbm_batch *b, int32_t run, double *f);
-/* Persistent grid size (blocks) and per-run tiles chosen by timing candidates;
+/* Persistent grid size (blocks), per-run tiles and step kernel (one or two
+ * nodes per thread, where both apply) chosen by timing candidates;
  * synchronises; state unchanged. */
 lbm_status lbm_batch_autotune(lbm_batch *b, int32_t trials, int32_t *best_blocks);
 lbm_status lbm_batch_set_blocks(lbm_batch *b, int32_t blocks);
+/* Step kernel of the batch: LBM_STEP_FUSED or LBM_STEP_PAIRS (two nodes per
+ * thread; needs FP32/F16S storage and even nx in every run, else
+ * LBM_ERR_UNSUPPORTED).  A new batch uses LBM_STEP_PAIRS where it applies.
+ * Rebuilds the work list and drops captured graphs; results are bit for bit
+ * the same in both modes. */
+lbm_status lbm_batch_set_step_mode(lbm_batch *b, int32_t mode);
+lbm_status lbm_batch_get_step_mode(const lbm_batch *b, int32_t *mode);
 lbm_status lbm_batch_kernel_time(lbm_batch *b, double *avg_ms, int64_t *launches);
 int64_t lbm_batch_nodes(const lbm_batch *b);
 

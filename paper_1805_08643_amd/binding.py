@@ -111,6 +111,8 @@ SIGNATURES = {
     "lbm_batch_read_populations": (_i32, [_vp, _i32, _vp]),
     "lbm_batch_autotune": (_i32, [_vp, _i32, _P(_i32)]),
     "lbm_batch_set_blocks": (_i32, [_vp, _i32]),
+    "lbm_batch_set_step_mode": (_i32, [_vp, _i32]),
+    "lbm_batch_get_step_mode": (_i32, [_vp, _P(_i32)]),
     "lbm_batch_kernel_time": (_i32, [_vp, _dp, _P(_i64)]),
     "lbm_batch_nodes": (_i64, [_vp]),
 }
@@ -503,6 +505,16 @@ class Batch:
 
     def set_blocks(self, blocks):
         _call("lbm_batch_set_blocks", _vp(self.h), int(blocks))
+
+    def set_step_mode(self, mode):
+        """mode: "fused" or "pairs"."""
+        _call("lbm_batch_set_step_mode", _vp(self.h), STEP_MODES[mode])
+        return self
+
+    def step_mode(self):
+        m = _i32(0)
+        _call("lbm_batch_get_step_mode", _vp(self.h), ctypes.byref(m))
+        return {v: k for k, v in STEP_MODES.items()}[m.value]
 
     def kernel_time(self):
         ms = ctypes.c_double(0)

@@ -787,6 +787,7 @@ struct lbm_batch {
     size_t smem = 0;
     int parity = 0;
     int item_nodes = 8192;
+    bool pairs = false;  // two x-adjacent nodes per thread
     long long nodes = 0;
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;
@@ -799,12 +800,14 @@ struct lbm_batch {
 
 namespace {
 
-lbm_tile batch_tile(const lbm_params &p, int item_nodes) {
+lbm_tile batch_tile(const lbm_params &p, int item_nodes, bool pairs) {
     lbm_tile t{};
-    if (p.nx <= 128) t.tx = p.nx;
+    if (pairs) t.tx = std::min(p.nx, 128);
+    else if (p.nx <= 128) t.tx = p.nx;
     else t.tx = default_tile(p.nx, p.ny, p.nz).tx;
-    t.ty = std::max(1, std::min(p.ny, STEP_MAX_THREADS / t.tx));
-    while (t.ty > 1 && block_threads(t.tx, t.ty) > STEP_MAX_THREADS) --t.ty;
+    const int per_row = pairs ? t.tx / 2 : t.tx;
+    t.ty = std::max(1, std::min(p.ny, STEP_MAX_THREADS / per_row));
+    while (t.ty > 1 && block_threads(t.tx, t.ty, pairs) > STEP_MAX_THREADS) --t.ty;
     const int cols = t.tx * t.ty;
     t.cz = std::max(1, std::min(p.nz, (item_nodes + cols / 2) / cols));
     return t;
@@ -841,7 +844,7 @@ lbm_status batch_build(lbm_batch *b) {
     long long nodes = 0;
     for (size_t k = 0; k < b->runs.size(); ++k) {
         lbm_ctx *c = b->runs[k];
-        c->tile = batch_tile(c->p, b->item_nodes);
+        c->tile = batch_tile(c->p, b->item_nodes, b->pairs);
         fill_grid(c->g, c->p, c->tile);
         RunDesc &d = b->desc[k];
         d.g = c->g;
@@ -850,7 +853,7 @@ lbm_status batch_build(lbm_batch *b) {
         d.offB = b->run_off[k] + c->L.B;
         d.tile_begin = tiles;
         tiles += c->g.ntiles;
-        threads = std::max(threads, block_threads(c->g.tx, c->g.ty));
+        threads = std::max(threads, block_threads(c->g.tx, c->g.ty, b->pairs));
         smem = std::max(smem, step_smem(c, c->g));
         nodes += c->g.N;
     }
@@ -869,21 +872,31 @@ lbm_status batch_build(lbm_batch *b) {
 lbm_status batch_launch(lbm_batch *b, hipStream_t st, int parity, int blocks) {
     const RunDesc *d = reinterpret_cast<const RunDesc *>(b->ws + b->desc_off);
     const int nr = (int)b->runs.size();
-#define LBM_BCASE(s, o)                                                                                      \
-    if (b->storage == s && b->op == o) {                                                                     \
-        hipLaunchKernelGGL((k_batch_step<s, o>), dim3(blocks), dim3(b->threads), b->smem, st, b->ws, d, nr,  \
-                           b->total_tiles, parity);                                                          \
-        HIP_TRY(hipGetLastError());                                                                          \
-        return LBM_OK;                                                                                       \
+#define LBM_BCASE(s, o, pr)                                                                                   \
+    if (b->storage == s && b->op == o && b->pairs == pr) {                                                    \
+        hipLaunchKernelGGL((k_batch_step<s, o, pr>), dim3(blocks), dim3(b->threads), b->smem, st, b->ws, d, nr, \
+                           b->total_tiles, parity);                                                           \
+        HIP_TRY(hipGetLastError());                                                                           \
+        return LBM_OK;                                                                                        \
     }
-    LBM_BCASE(ST_F64, OP_NONORTH)
-    LBM_BCASE(ST_F64, OP_ORTH)
-    LBM_BCASE(ST_F32, OP_NONORTH)
-    LBM_BCASE(ST_F32, OP_ORTH)
-    LBM_BCASE(ST_F16S, OP_NONORTH)
-    LBM_BCASE(ST_F16S, OP_ORTH)
+    LBM_BCASE(ST_F64, OP_NONORTH, false)
+    LBM_BCASE(ST_F64, OP_ORTH, false)
+    LBM_BCASE(ST_F32, OP_NONORTH, false)
+    LBM_BCASE(ST_F32, OP_ORTH, false)
+    LBM_BCASE(ST_F16S, OP_NONORTH, false)
+    LBM_BCASE(ST_F16S, OP_ORTH, false)
+    LBM_BCASE(ST_F32, OP_NONORTH, true)
+    LBM_BCASE(ST_F32, OP_ORTH, true)
+    LBM_BCASE(ST_F16S, OP_NONORTH, true)
+    LBM_BCASE(ST_F16S, OP_ORTH, true)
 #undef LBM_BCASE
     return fail(LBM_ERR_UNSUPPORTED, "no batched kernel for storage %d op %d", b->storage, b->op);
+}
+
+bool batch_pairs_apply(const lbm_params *runs, int n) {
+    for (int k = 0; k < n; ++k)
+        if (!pairs_apply(runs[k])) return false;
+    return true;
 }
 
 int default_blocks(const lbm_batch *b) {
@@ -947,6 +960,7 @@ lbm_status lbm_batch_create(const lbm_params *runs, int32_t n, void *dev_ws, siz
     b->stream = static_cast<hipStream_t>(hip_stream);
     b->op = runs[0].op;
     b->storage = runs[0].storage;
+    b->pairs = batch_pairs_apply(runs, n);
     for (int k = 0; k < n; ++k) {
         lbm_ctx *c = nullptr;
         s = lbm_create(&runs[k], b->ws + b->run_off[k], layout_of(runs[k]).total, hip_stream, &c);
@@ -1062,6 +1076,28 @@ lbm_status lbm_batch_set_blocks(lbm_batch *b, int32_t blocks) {
     return LBM_OK;
 }
 
+lbm_status lbm_batch_set_step_mode(lbm_batch *b, int32_t mode) {
+    if (!b) return fail(LBM_ERR_INVALID_ARG, "batch is NULL");
+    if (mode != LBM_STEP_FUSED && mode != LBM_STEP_PAIRS)
+        return fail(LBM_ERR_INVALID_ARG, "batched runs take LBM_STEP_FUSED or LBM_STEP_PAIRS, got %d", mode);
+    if (mode == LBM_STEP_PAIRS) {
+        for (size_t k = 0; k < b->runs.size(); ++k)
+            if (!pairs_apply(b->runs[k]->p))
+                return fail(LBM_ERR_UNSUPPORTED, "run %zu: pair mode needs FP32/F16S storage and even nx", k);
+    }
+    b->pairs = mode == LBM_STEP_PAIRS;
+    lbm_status s = batch_build(b);
+    if (s) return s;
+    b->blocks = std::min(b->blocks, b->total_tiles);
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_get_step_mode(const lbm_batch *b, int32_t *mode) {
+    if (!b || !mode) return fail(LBM_ERR_INVALID_ARG, "null argument");
+    *mode = b->pairs ? LBM_STEP_PAIRS : LBM_STEP_FUSED;
+    return LBM_OK;
+}
+
 lbm_status lbm_batch_autotune(lbm_batch *b, int32_t trials, int32_t *best_blocks) {
     if (!b) return fail(LBM_ERR_INVALID_ARG, "batch is NULL");
     if (trials < 1) return fail(LBM_ERR_INVALID_ARG, "trials < 1");
@@ -1071,8 +1107,15 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t trials, int32_t *best_blocks
     const int items[] = {4096, 8192, 16384, 32768};
     float best = 1e30f;
     int best_items = b->item_nodes, best_blk = b->blocks;
+    bool best_pairs = b->pairs;
+    std::vector<bool> modes{false};
+    bool all_pairs = true;
+    for (lbm_ctx *c : b->runs) all_pairs = all_pairs && pairs_apply(c->p);
+    if (all_pairs) modes.push_back(true);
     lbm_status s;
+    for (bool pr : modes)
     for (int it : items) {
+        b->pairs = pr;
         b->item_nodes = it;
         if ((s = batch_build(b))) return s;
         const int cands[] = {256, 512, 1024, 2048, 4096, b->total_tiles};
@@ -1091,11 +1134,13 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t trials, int32_t *best_blocks
                 best = ms;
                 best_items = it;
                 best_blk = blk;
+                best_pairs = pr;
             }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    b->pairs = best_pairs;
     b->item_nodes = best_items;
     if ((s = batch_build(b))) return s;
     b->blocks = best_blk;

@@ -696,7 +696,7 @@ struct RunDesc {
     int pad;
 };
 
-template <int S, int OP>
+template <int S, int OP, bool PAIRS>
 __global__ void LBM_STEP_ATTR
     k_batch_step(unsigned char *__restrict__ ws, const RunDesc *__restrict__ runs, int nruns, int total_tiles,
                  int parity) {
@@ -722,7 +722,10 @@ __global__ void LBM_STEP_ATTR
         P.load(rd.pd);
         const T *src = reinterpret_cast<const T *>(ws + (parity ? rd.offB : rd.offA));
         T *dst = reinterpret_cast<T *>(ws + (parity ? rd.offA : rd.offB));
-        tile_march<S, OP, false>(src, dst, nullptr, g, P, item - rd.tile_begin, ps);
+        if constexpr (PAIRS)
+            tile_march2<S, OP, false>(src, dst, nullptr, g, P, item - rd.tile_begin, ps);
+        else
+            tile_march<S, OP, false>(src, dst, nullptr, g, P, item - rd.tile_begin, ps);
         lds_barrier();  // the next item reuses the LDS ring
     }
 }

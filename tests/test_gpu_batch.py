@@ -72,6 +72,28 @@ def test_batch_bit_identical_to_single_lattices(storage):
     b.close()
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16s"])
+def test_batch_step_modes_bit_identical(storage):
+    """Two nodes per thread (default for even sizes) and one node per thread
+    give the same populations in a batch."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    runs = _runs(storage, sizes=(32, 48, 20, 36))
+    out = {}
+    for mode in ("pairs", "fused"):
+        b = Batch([r[0] for r in runs])
+        assert b.step_mode() == "pairs"
+        b.set_step_mode(mode)
+        assert b.step_mode() == mode
+        for k, (p, init) in enumerate(runs):
+            b.init_fields(k, *li.init_fields(p, init))
+        b.step(5, 4)
+        out[mode] = [b.pops(k) for k in range(len(runs))]
+        b.close()
+    for k in range(len(runs)):
+        assert np.array_equal(out["pairs"][k], out["fused"][k]), k
+
+
 def test_batch_full_workload_sampled_runs():
     """The 256-run workload (L in {32, 48, 64, 96}), FP32: eight runs checked
     against the oracle after 3 steps."""
