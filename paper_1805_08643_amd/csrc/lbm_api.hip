@@ -570,8 +570,8 @@ lbm_status lbm_diagnostics(lbm_ctx *c, const lbm_diag_request *req, lbm_diag *ou
         hipLaunchKernelGGL((k_diag<S.value, W.value>), dim3(nblk), dim3(DIAG_THREADS), 0, c->stream,
                            (const T *)c->state(), (const R *)c->psi(), (const R *)c->gpsi(), c->partial(), c->g,
                            c->pd, rq);
-        hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, c->stream, (const double *)c->partial(), nblk,
-                           c->dout());
+        hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(DIAG_FINAL_THREADS), 0, c->stream,
+                           (const double *)c->partial(), nblk, c->dout());
         HIP_TRY(hipGetLastError());
         return LBM_OK;
     });

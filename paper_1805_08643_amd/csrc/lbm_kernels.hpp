@@ -1158,12 +1158,36 @@ __global__ void __launch_bounds__(DIAG_THREADS)
     }
 }
 
-__global__ void k_diag_final(const double *__restrict__ partial, int nblocks, double *__restrict__ out) {
-    const int k = threadIdx.x;
-    if (k >= NDIAG) return;
-    double v = 0.0;
-    for (int b = 0; b < nblocks; ++b) v = (k == 4) ? fmax(v, partial[(size_t)b * NDIAG + k]) : v + partial[(size_t)b * NDIAG + k];
-    out[k] = v;
+// Second pass of the diagnostics: DIAG_FINAL_THREADS threads each fold a
+// fixed, strided subset of the block partials, then a tree in LDS combines
+// them in a fixed order, so the result does not depend on timing.
+constexpr int DIAG_FINAL_THREADS = 256;
+__global__ void __launch_bounds__(DIAG_FINAL_THREADS)
+    k_diag_final(const double *__restrict__ partial, int nblocks, double *__restrict__ out) {
+    __shared__ double red[NDIAG][DIAG_FINAL_THREADS];
+    const int t = threadIdx.x;
+    double v[NDIAG];
+#pragma unroll
+    for (int k = 0; k < NDIAG; ++k) v[k] = 0.0;
+    for (int b = t; b < nblocks; b += DIAG_FINAL_THREADS) {
+#pragma unroll
+        for (int k = 0; k < NDIAG; ++k) {
+            const double p = partial[(size_t)b * NDIAG + k];
+            v[k] = (k == 4) ? fmax(v[k], p) : v[k] + p;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NDIAG; ++k) red[k][t] = v[k];
+    __syncthreads();
+    for (int stride = DIAG_FINAL_THREADS / 2; stride > 0; stride >>= 1) {
+        if (t < stride) {
+#pragma unroll
+            for (int k = 0; k < NDIAG; ++k)
+                red[k][t] = (k == 4) ? fmax(red[k][t], red[k][t + stride]) : red[k][t] + red[k][t + stride];
+        }
+        __syncthreads();
+    }
+    if (t < NDIAG) out[t] = red[t][0];
 }
 
 }  // namespace lbm

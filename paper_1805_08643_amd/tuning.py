@@ -5,13 +5,13 @@ either kernel give the same populations; these are the fastest found."""
 STEP_TILES = {
     # (workload, storage, mode) -> (tx, ty, cz); mode "fused": one node per
     # thread, "pairs": two x-adjacent nodes per thread (tx counts nodes)
-    ("droplet_32", "f64", "fused"): (32, 8, 8),
-    ("laplace_128", "f64", "fused"): (64, 4, 16),
+    ("droplet_32", "f64", "fused"): (32, 2, 4),
+    ("laplace_128", "f64", "fused"): (128, 4, 16),
     ("laplace_128", "f32", "fused"): (64, 4, 16),
     ("laplace_128", "f32", "pairs"): (64, 8, 8),
     ("laplace_128", "f16s", "fused"): (64, 8, 16),
     ("laplace_128", "f16s", "pairs"): (64, 8, 8),
-    ("two_droplets_256", "f64", "fused"): (128, 4, 64),
+    ("two_droplets_256", "f64", "fused"): (128, 4, 128),
     ("two_droplets_256", "f32", "fused"): (64, 4, 128),
     ("two_droplets_256", "f32", "pairs"): (128, 8, 64),
     ("two_droplets_256", "f16s", "fused"): (64, 4, 32),
