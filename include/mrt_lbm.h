@@ -89,6 +89,15 @@ typedef struct lbm_params {
     double gravity[3];      /* body acceleration g; body force rho g */
     double theta_wall_deg;  /* prescribed contact angle theta_a, Eq. (57) */
     double ghost_rho_min;   /* lower clamp of the Eq. (57) ghost density */
+    /* Density-dependent kinematic viscosity for runs with nu_V != nu_L
+     * (Sec. IV.D varies nu_V / nu_L without giving the rule; this is the
+     * library's reading).  nu_ratio = 0 or 1: s_nu everywhere.  Otherwise
+     * nu_L = (1/s_nu - 1/2)/3 (Eq. (54)), nu_V = nu_ratio nu_L, and a node of
+     * density rho takes nu = nu_V + t (nu_L - nu_V) with
+     * t = (rho - visc_rho_V) / (visc_rho_L - visc_rho_V) clamped to [0, 1];
+     * its stress rows relax at 1 / (3 nu + 1/2).  nu_ratio must be >= 0 and
+     * finite; when it is active, 0 <= visc_rho_V < visc_rho_L. */
+    double nu_ratio, visc_rho_L, visc_rho_V;
 } lbm_params;
 
 /* Launch shape of the fused step: tx * ty threads per block, one thread per

@@ -58,6 +58,16 @@ typedef struct {
     double rates[Q];                   /* diagonal of Lambda */
     double M[Q * Q];                   /* M[k*Q + a] */
     double Minv[Q * Q];                /* Minv[a*Q + k] */
+    /* Density-dependent kinematic viscosity (a reading: the paper varies
+     * nu_V / nu_L in Sec. IV.D without stating the rule).  nu_ratio <= 0 or
+     * == 1: the rates above everywhere.  Otherwise nu_L = (1/s - 1/2)/3 with
+     * s the rate of the rows in nu_mask, nu_V = nu_ratio nu_L, and at a node
+     * of density rho, nu = nu_V + t (nu_L - nu_V) with
+     * t = (rho - visc_rho_V) / (visc_rho_L - visc_rho_V) clamped to [0, 1];
+     * those rows then relax at 1 / (3 nu + 1/2) (Eq. (54)). */
+    int32_t nu_mask;                   /* bit k set: row k relaxes at s_nu */
+    int32_t reserved2;
+    double nu_ratio, visc_rho_L, visc_rho_V;
 } oracle_params;
 
 static int opp_of(int a) {
@@ -225,6 +235,28 @@ static double psi_at(const oracle_params *p, const fields_t *w, int64_t x, int64
     return w->psi[(z * ny + y) * nx + x];
 }
 
+/* Relaxation rates at a node of density rho (see nu_ratio above). */
+static void local_rates(const oracle_params *p, double rho, double r[Q]) {
+    for (int k = 0; k < Q; ++k) r[k] = p->rates[k];
+    if (p->nu_ratio <= 0.0 || p->nu_ratio == 1.0) return;
+    int k0 = -1;
+    for (int k = 0; k < Q; ++k)
+        if (p->nu_mask & (1 << k)) {
+            k0 = k;
+            break;
+        }
+    if (k0 < 0) return;
+    const double nu_L = (1.0 / p->rates[k0] - 0.5) / 3.0;
+    const double nu_V = p->nu_ratio * nu_L;
+    double t = (rho - p->visc_rho_V) / (p->visc_rho_L - p->visc_rho_V);
+    if (t < 0.0) t = 0.0;
+    if (t > 1.0) t = 1.0;
+    const double nu = nu_V + t * (nu_L - nu_V);
+    const double s = 1.0 / (3.0 * nu + 0.5);
+    for (int k = 0; k < Q; ++k)
+        if (p->nu_mask & (1 << k)) r[k] = s;
+}
+
 /* Collision at one node: fin[19] -> fout[19]; optional macroscopic outputs. */
 static void collide_node(const oracle_params *p, const fields_t *w, int64_t x, int64_t y, int64_t z,
                          const double fin[Q], double fout[Q], double *u_out, double *F_out) {
@@ -262,8 +294,10 @@ static void collide_node(const oracle_params *p, const fields_t *w, int64_t x, i
     }
     meq_of(p, rho, u, meq);
     source_of(p, u, F, Fm2_over_psi2, S);
+    double r[Q];
+    local_rates(p, rho, r);
     for (int k = 0; k < Q; ++k)
-        ms[k] = m[k] - p->rates[k] * (m[k] - meq[k]) + (1.0 - 0.5 * p->rates[k]) * S[k];
+        ms[k] = m[k] - r[k] * (m[k] - meq[k]) + (1.0 - 0.5 * r[k]) * S[k];
     for (int a = 0; a < Q; ++a) {
         double s = 0.0;
         for (int k = 0; k < Q; ++k) s += p->Minv[a * Q + k] * ms[k];

@@ -150,6 +150,14 @@ def orth_rates(s_e, s_nu, s_q, s_pi, s_eps, s_m) -> list[float]:
     return [r[n] for n in ORTH_ROW_NAMES]
 
 
+# Rows relaxed at s_nu (the five second-order stress moments).
+NONORTH_NU_ROWS = (5, 6, 7, 8, 9)
+
+
+def orth_nu_rows() -> tuple[int, ...]:
+    return tuple(ORTH_ROW_NAMES.index(n) for n in ("3pxx", "pww", "pxy", "pyz", "pxz"))
+
+
 def orth_sigma_rows() -> tuple[int, int]:
     """Rows of the orthogonal basis that receive the thermodynamic-consistency
     correction: the image under ``orth_M`` of the velocity-space vector that

@@ -38,6 +38,8 @@ class OracleParams(ctypes.Structure):
         ("rates", ctypes.c_double * Q),
         ("M", ctypes.c_double * (Q * Q)),
         ("Minv", ctypes.c_double * (Q * Q)),
+        ("nu_mask", ctypes.c_int32), ("reserved2", ctypes.c_int32),
+        ("nu_ratio", ctypes.c_double), ("visc_rho_L", ctypes.c_double), ("visc_rho_V", ctypes.c_double),
     ]
 
 
@@ -124,6 +126,11 @@ def make_params(cfg: dict, nthreads: int = 0) -> OracleParams:
     M, Mi = _matrices(op)
     ctypes.memmove(p.M, M.ctypes.data, M.nbytes)
     ctypes.memmove(p.Minv, Mi.ctypes.data, Mi.nbytes)
+    rows = moments.NONORTH_NU_ROWS if op == "nonorth" else moments.orth_nu_rows()
+    p.nu_mask = sum(1 << k for k in rows)
+    p.nu_ratio = float(cfg.get("nu_ratio", 0.0))
+    p.visc_rho_L = float(cfg.get("visc_rho_L", 0.0))
+    p.visc_rho_V = float(cfg.get("visc_rho_V", 0.0))
     return p
 
 

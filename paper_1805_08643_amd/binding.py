@@ -38,6 +38,7 @@ class LbmParams(ctypes.Structure):
         ("psi0", ctypes.c_double), ("rho0", ctypes.c_double), ("sigma", ctypes.c_double),
         ("gravity", ctypes.c_double * 3), ("theta_wall_deg", ctypes.c_double),
         ("ghost_rho_min", ctypes.c_double),
+        ("nu_ratio", ctypes.c_double), ("visc_rho_L", ctypes.c_double), ("visc_rho_V", ctypes.c_double),
     ]
 
 
@@ -312,6 +313,9 @@ def make_params(cfg: dict) -> LbmParams:
         p.gravity[d] = g[d]
     p.theta_wall_deg = cfg.get("theta_wall_deg", 90.0)
     p.ghost_rho_min = cfg.get("ghost_rho_min", 0.0)
+    p.nu_ratio = cfg.get("nu_ratio", 0.0)
+    p.visc_rho_L = cfg.get("visc_rho_L", 0.0)
+    p.visc_rho_V = cfg.get("visc_rho_V", 0.0)
     return p
 
 

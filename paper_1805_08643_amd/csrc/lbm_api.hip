@@ -77,6 +77,12 @@ lbm_status validate(const lbm_params *p) {
             return fail(LBM_ERR_INVALID_ARG, "psi0, rho0 must be finite");
     }
     if (!std::isfinite(p->sigma)) return fail(LBM_ERR_INVALID_ARG, "sigma not finite");
+    if (!(std::isfinite(p->nu_ratio) && p->nu_ratio >= 0.0))
+        return fail(LBM_ERR_INVALID_ARG, "nu_ratio = %g must be finite and >= 0", p->nu_ratio);
+    if (p->nu_ratio > 0.0 && p->nu_ratio != 1.0 &&
+        !(std::isfinite(p->visc_rho_L) && p->visc_rho_V >= 0.0 && p->visc_rho_L > p->visc_rho_V))
+        return fail(LBM_ERR_INVALID_ARG, "variable viscosity needs 0 <= visc_rho_V < visc_rho_L (got %g, %g)",
+                    p->visc_rho_V, p->visc_rho_L);
     for (int d = 0; d < 3; ++d)
         if (!std::isfinite(p->gravity[d])) return fail(LBM_ERR_INVALID_ARG, "gravity not finite");
     if (!(p->theta_wall_deg > 0.0 && p->theta_wall_deg < 180.0))
@@ -115,6 +121,15 @@ PhysD make_phys(const lbm_params &p) {
     d.rho_ref = p.storage == LBM_STORE_F16S ? p.rho_ref : 0.0;
     d.h_exp = p.storage == LBM_STORE_F16S ? p.f16_exp : 0;
     d.psi_form = p.psi_form;
+    // Density-dependent viscosity: nu = nuV + t dnu, t = (rho - vrhoV) vinv in [0, 1]
+    d.visc = p.nu_ratio > 0.0 && p.nu_ratio != 1.0;
+    if (d.visc) {
+        const double nuL = (1.0 / p.s_nu - 0.5) / 3.0;
+        d.nuV = p.nu_ratio * nuL;
+        d.dnu = nuL - d.nuV;
+        d.vrhoV = p.visc_rho_V;
+        d.vinv = 1.0 / (p.visc_rho_L - p.visc_rho_V);
+    }
     return d;
 }
 

@@ -50,7 +50,12 @@ struct PhysD {  // host-filled, double
     double tan_wall, ghost_rho_min, rho_ref;
     int psi_form;
     int h_exp;  // F16S exponent offset: stored h = (fbar - w rho_ref) * 2^h_exp
+    int visc;   // density-dependent viscosity on
+    double nuV, dnu, vrhoV, vinv;
 };
+
+__device__ inline float r_rcp(float v);
+__device__ inline double r_rcp(double v);
 
 template <class R> struct Phys {
     R G, a, b4, RT, psi0, rho0, two_over_G;
@@ -62,6 +67,8 @@ template <class R> struct Phys {
     R hs, hsi;           // 2^h_exp and 2^-h_exp (exact powers of two)
     R shs[3];            // shift * 2^h_exp
     int psi_form;
+    int visc;
+    R nuV, dnu, vrhoV, vinv;
     __device__ inline void load(const PhysD &d) {
         G = (R)d.G;
         a = (R)d.a;
@@ -93,6 +100,20 @@ template <class R> struct Phys {
         shs[1] = shift[1] * hs;
         shs[2] = shift[2] * hs;
         psi_form = d.psi_form;
+        visc = d.visc;
+        nuV = (R)d.nuV;
+        dnu = (R)d.dnu;
+        vrhoV = (R)d.vrhoV;
+        vinv = (R)d.vinv;
+    }
+    // Rate of the stress rows at a node of density rho: s_nu, or with a
+    // density-dependent viscosity 1 / (3 nu + 1/2) with nu linear in rho
+    // between (vrhoV, nuV) and (vrhoV + 1/vinv, nuV + dnu), clamped.
+    __device__ inline R snu_at(R rho) const {
+        if (!visc) return s_nu;
+        R t = (rho - vrhoV) * vinv;
+        t = t < (R)0 ? (R)0 : (t > (R)1 ? (R)1 : t);
+        return r_rcp((R)3 * (nuV + t * dnu) + (R)0.5);
     }
     __device__ inline R sh(int a_) const { return a_ == 0 ? shift[0] : (a_ <= 6 ? shift[1] : shift[2]); }
     __device__ inline R shh(int a_) const { return a_ == 0 ? shs[0] : (a_ <= 6 ? shs[1] : shs[2]); }
@@ -358,19 +379,20 @@ __device__ inline void collide(R f[Q], R rho, R Fx, R Fy, R Fz, R acc2, const Ph
     dm[1] = Fx;
     dm[2] = Fy;
     dm[3] = Fz;
+    const R snu = P.snu_at(rho);
     if (OP == OP_NONORTH) {
-        const R ce = (R)1 - (R)0.5 * P.s_e, cn = (R)1 - (R)0.5 * P.s_nu;
+        const R ce = (R)1 - (R)0.5 * P.s_e, cn = (R)1 - (R)0.5 * snu;
         const R cq = (R)1 - (R)0.5 * P.s_q, cp = (R)1 - (R)0.5 * P.s_pi;
         // second order, Eqs. (8), (13), (14), (16)
         R m4 = pr.a12 + pr.a34 + pr.a56 + (R)2 * (pr.s16 + pr.s17 + pr.s18);
         R m5 = (R)2 * pr.a12 - pr.a34 - pr.a56 + pr.s16 + pr.s17 - (R)2 * pr.s18;
         R m6 = pr.a34 - pr.a56 + pr.s16 - pr.s17;
         dm[4] = P.s_e * (rho + rho * u2 - m4) + ce * (R)2 * Fu + P.ksig_e * acc2;
-        dm[5] = P.s_nu * (rho * ((R)2 * uxx - uyy - uzz) - m5) + cn * (R)2 * ((R)2 * Fux - Fuy - Fuz);
-        dm[6] = P.s_nu * (rho * (uyy - uzz) - m6) + cn * (R)2 * (Fuy - Fuz);
-        dm[7] = P.s_nu * (rho * ux * uy - pr.p7) + cn * (Fx * uy + Fy * ux);
-        dm[8] = P.s_nu * (rho * ux * uz - pr.p8) + cn * (Fx * uz + Fz * ux);
-        dm[9] = P.s_nu * (rho * uy * uz - pr.p9) + cn * (Fy * uz + Fz * uy);
+        dm[5] = snu * (rho * ((R)2 * uxx - uyy - uzz) - m5) + cn * (R)2 * ((R)2 * Fux - Fuy - Fuz);
+        dm[6] = snu * (rho * (uyy - uzz) - m6) + cn * (R)2 * (Fuy - Fuz);
+        dm[7] = snu * (rho * ux * uy - pr.p7) + cn * (Fx * uy + Fy * ux);
+        dm[8] = snu * (rho * ux * uz - pr.p8) + cn * (Fx * uz + Fz * ux);
+        dm[9] = snu * (rho * uy * uz - pr.p9) + cn * (Fy * uz + Fz * uy);
         // third order, Eq. (9)
         const R rx = third * rho * ux, ry = third * rho * uy, rz = third * rho * uz;
         const R qx = cq * third * Fx, qy = cq * third * Fy, qz = cq * third * Fz;
@@ -395,7 +417,7 @@ __device__ inline void collide(R f[Q], R rho, R Fx, R Fy, R Fz, R acc2, const Ph
         // S = M_orth G (Guo forcing); Eq. (16) term carried to the e and eps
         // rows by the image of the non-orthogonal column (19, -16).
         const R ce = (R)1 - (R)0.5 * P.s_e, cE = (R)1 - (R)0.5 * P.s_eps;
-        const R cn = (R)1 - (R)0.5 * P.s_nu, cq = (R)1 - (R)0.5 * P.s_q;
+        const R cn = (R)1 - (R)0.5 * snu, cq = (R)1 - (R)0.5 * P.s_q;
         const R cp = (R)1 - (R)0.5 * P.s_pi;
         const R sumax = pr.a12 + pr.a34 + pr.a56, sumdg = pr.s16 + pr.s17 + pr.s18;
         const R e = (R)(-30) * f[0] - (R)11 * sumax + (R)8 * sumdg;
@@ -420,13 +442,13 @@ __device__ inline void collide(R f[Q], R rho, R Fx, R Fy, R Fz, R acc2, const Ph
         dm[6] = P.s_q * (-two3 * rho * uy - qym) - cq * two3 * Fy;
         dm[7] = Fz;
         dm[8] = P.s_q * (-two3 * rho * uz - qzm) - cq * two3 * Fz;
-        dm[9] = P.s_nu * (rho * dxx - pxx) + cn * Sxx;
+        dm[9] = snu * (rho * dxx - pxx) + cn * Sxx;
         dm[10] = P.s_pi * ((R)(-0.5) * rho * dxx - ixx) - cp * (R)0.5 * Sxx;
-        dm[11] = P.s_nu * (rho * dww - pww) + cn * Sww;
+        dm[11] = snu * (rho * dww - pww) + cn * Sww;
         dm[12] = P.s_pi * ((R)(-0.5) * rho * dww - iww) - cp * (R)0.5 * Sww;
-        dm[13] = P.s_nu * (rho * ux * uy - pr.p7) + cn * (Fx * uy + Fy * ux);
-        dm[14] = P.s_nu * (rho * uy * uz - pr.p9) + cn * (Fy * uz + Fz * uy);
-        dm[15] = P.s_nu * (rho * ux * uz - pr.p8) + cn * (Fx * uz + Fz * ux);
+        dm[13] = snu * (rho * ux * uy - pr.p7) + cn * (Fx * uy + Fy * ux);
+        dm[14] = snu * (rho * uy * uz - pr.p9) + cn * (Fy * uz + Fz * uy);
+        dm[15] = snu * (rho * ux * uz - pr.p8) + cn * (Fx * uz + Fz * ux);
         dm[16] = -P.s_m * mx;
         dm[17] = -P.s_m * my;
         dm[18] = -P.s_m * mz;

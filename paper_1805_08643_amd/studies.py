@@ -22,6 +22,8 @@ returns plain dicts (one line of JSON per run is printed as it finishes).
   table2     Sec. IV.D, Table II and Fig. 6: droplet at T = 0.6 T_c, a = 0.25,
              120^3, r0 = 40, W = 5, sigma = 0.105, both operators;
              coexistence densities and maximum spurious velocity.
+  viscosity_ratio  Sec. IV.D after Fig. 6: the same droplet with nu_L = 0.01
+             and nu_V / nu_L in {1, 2, 5, 10}; maximum spurious velocity.
   laplace_cs Laplace law with the C-S EOS at T = 0.7 T_c, a = 0.5, 128^3,
              r0 in 12..28, FP64 and FP32 storage, both operators.
   contact_cs Sessile droplet with the C-S EOS at T = 0.7 T_c on
@@ -341,6 +343,49 @@ def table2(ops=("nonorth", "orth"), nus=(0.01, 1.0 / 30.0, 0.05, 0.1, 0.15), ste
     return out
 
 
+def viscosity_ratio(ops=("nonorth", "orth"), ratios=(1.0, 2.0, 5.0, 10.0), nu_L=0.01, steps=30000, n=120,
+                    warm_nu=0.1):
+    """Sec. IV.D after Fig. 6: the Table II droplet with liquid viscosity
+    nu_L = 0.01 and vapour viscosity nu_ratio nu_L, nu linear in rho between
+    the coexistence densities (the library's reading); maximum spurious
+    velocity against nu_V / nu_L.  A run whose cold start diverges restarts
+    from the state reached after `steps` at uniform nu = warm_nu."""
+    import lbm_inputs as li
+    rl0, rv0 = li.coexistence(0.6)
+    c = (n / 2, n / 2, n / 2)
+
+    def cfg_for(op, ratio, nu):
+        return _params(n, op=op, T_over_Tc=0.6, eos_a=0.25, sigma=0.105, tau_nu=tau_for_nu(nu), storage="f64",
+                       nu_ratio=ratio, visc_rho_L=rl0, visc_rho_V=rv0, **PAPER_RATES)
+
+    out = []
+    for op in ops:
+        warm = None
+        for ratio in ratios:
+            lat = _lattice(cfg_for(op, ratio, nu_L))
+            lat.init_droplets([dict(center=c, r0=40.0)], rl0, rv0, 5.0)
+            lat.step(steps)
+            obs = _droplet(lat, c, 40.0, 5.0)
+            lat.close()
+            start = "cold"
+            if obs["nonfinite"]:
+                if warm is None:
+                    w = _lattice(cfg_for(op, 1.0, warm_nu))
+                    w.init_droplets([dict(center=c, r0=40.0)], rl0, rv0, 5.0)
+                    w.step(steps)
+                    warm = w.save_state()
+                    w.close()
+                lat = _lattice(cfg_for(op, ratio, nu_L))
+                lat.load_state(warm)
+                lat.step(steps)
+                obs = _droplet(lat, c, 40.0, 5.0)
+                lat.close()
+                start = f"state after {steps} steps at nu={warm_nu}"
+            out.append(_emit(dict(study="viscosity_ratio", op=op, nu_L=nu_L, nu_ratio=ratio, steps=steps,
+                                  start=start, **obs)))
+    return out
+
+
 def laplace_cs(ops=("nonorth", "orth"), storages=("f64", "f32"), radii=(24, 28, 32, 36, 40), steps=20000):
     """Radii from 24: droplets of radius 12 to 20 evaporate in the 128^3 box
     (Kelvin effect, as in `laplace`)."""
@@ -417,8 +462,8 @@ def precision(steps=(100, 500, 1000, 2000), n=256, crop=64):
     return out
 
 
-STUDIES = {f.__name__: f for f in (table1, stability, laplace, spurious, contact, flat, table2, laplace_cs,
-                                   contact_cs, precision)}
+STUDIES = {f.__name__: f for f in (table1, stability, laplace, spurious, contact, flat, table2, viscosity_ratio,
+                                   laplace_cs, contact_cs, precision)}
 
 
 def main(argv=None):

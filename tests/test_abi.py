@@ -41,7 +41,7 @@ def test_params_default_and_workspace_size():
 
 @pytest.mark.parametrize("field,value", [("nx", 0), ("s_nu", 2.0), ("s_e", 0.0), ("G", 0.5), ("op", 7),
                                          ("storage", 9), ("T_over_Tc", -1.0), ("theta_wall_deg", 180.0),
-                                         ("f16_exp", 30)])
+                                         ("f16_exp", 30), ("nu_ratio", -1.0), ("nu_ratio", float("nan"))])
 def test_invalid_params_rejected(field, value):
     p = binding.lbm_params_default()
     setattr(p, field, value)
@@ -49,6 +49,18 @@ def test_invalid_params_rejected(field, value):
     st = binding.lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n))
     assert st == -1
     assert binding.lbm_last_error()
+
+
+def test_variable_viscosity_needs_density_range():
+    p = binding.lbm_params_default()
+    n = ctypes.c_size_t(0)
+    p.nu_ratio = 10.0
+    p.visc_rho_L, p.visc_rho_V = 0.1, 0.4  # inverted
+    assert binding.lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == -1
+    p.visc_rho_L, p.visc_rho_V = 0.4, 0.003
+    assert binding.lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == 0
+    p.nu_ratio, p.visc_rho_L, p.visc_rho_V = 1.0, 0.0, 0.0  # uniform: range unused
+    assert binding.lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == 0
 
 
 def test_walls_need_two_planes():

@@ -107,6 +107,11 @@ CASES = {
                                    dict(li.c3_two_droplets(n=64)[1]), (32, 8, 8)),
     "walls_40x33x19_60deg": lambda op: (*li.c4_sessile(60.0, nx=40, ny=33, nz=19, r0=8.0), (16, 8, 7)),
     "walls_37x20x12_120deg": lambda op: (*li.c4_sessile(120.0, nx=37, ny=20, nz=12, r0=6.0), (32, 4, 5)),
+    # density-dependent viscosity: nu_L = 0.01 in the liquid, nu_V = 10 nu_L
+    "visc_two_droplets_48": lambda op: (
+        dict(li.c3_two_droplets(n=48, op=op)[0], tau_nu=0.53, nu_ratio=10.0,
+             visc_rho_L=li.coexistence(0.6)[0], visc_rho_V=li.coexistence(0.6)[1]),
+        li.c3_two_droplets(n=48)[1], (16, 8, 12)),
 }
 
 
@@ -151,7 +156,7 @@ def test_fp64_parity_500_steps_droplet_32():
 
 @pytest.mark.parametrize("mode", ["fused", "pairs"])
 @pytest.mark.parametrize("op", ["nonorth", "orth"])
-@pytest.mark.parametrize("name", ["droplet_32", "ragged_70x37x21", "walls_40x33x19_60deg"])
+@pytest.mark.parametrize("name", ["droplet_32", "ragged_70x37x21", "walls_40x33x19_60deg", "visc_two_droplets_48"])
 def test_fp32_parity(name, op, mode):
     cfg, rho, u, tile = _case(name, op, "f32")
     cps = [1, 10]

@@ -326,3 +326,51 @@ def test_step_sampled_equals_full_step(walls):
     idx = np.arange(f0.shape[1])
     samp = ref.step_sampled(p, f0, idx)
     np.testing.assert_array_equal(samp.T, full)
+
+
+# ---------------------------------------------------------------------------
+# Density-dependent viscosity (the reading of the nu_V / nu_L runs of Sec. IV.D:
+# nu linear in rho between visc_rho_V and visc_rho_L, constant outside).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("op", ["nonorth", "orth"])
+def test_variable_viscosity_shear_wave_at_mid_density(op):
+    """At a uniform density halfway between visc_rho_V and visc_rho_L the
+    shear wave decays at the mean of nu_L and nu_V (Eq. (54))."""
+    L, s_nu, ratio = 64, 1.6, 4.0
+    nu_L = (1 / s_nu - 0.5) / 3
+    cfg = _single_phase(1, L, 1, op, s_e=0.9, s_nu=s_nu)
+    cfg.update(nu_ratio=ratio, visc_rho_L=1.5, visc_rho_V=0.5)
+    p = ref.make_params(cfg)
+    k = 2 * math.pi / L
+    y = np.arange(L)
+    u = np.zeros((3, L))
+    u[0] = 1e-4 * np.sin(k * y)
+    f = ref.equilibrium(p, np.ones(L), u)
+    f = ref.step(p, f, 50)
+    a1 = (ref.fields(p, f)["u"][0] * np.sin(k * y)).sum()
+    f = ref.step(p, f, 200)
+    a2 = (ref.fields(p, f)["u"][0] * np.sin(k * y)).sum()
+    nu_meas = -math.log(a2 / a1) / (k * k * 200)
+    assert abs(nu_meas / (0.5 * (nu_L + ratio * nu_L)) - 1) < 0.01
+
+
+@pytest.mark.parametrize("op", ["nonorth", "orth"])
+@pytest.mark.parametrize("side", ["vapour", "liquid"])
+def test_variable_viscosity_reduces_to_constant_rates_outside_range(op, side):
+    """Below visc_rho_V every node relaxes the stress rows at the rate of
+    nu_V = ratio nu_L, above visc_rho_L at s_nu: one step equals a
+    constant-rate step with that rate."""
+    s_nu, ratio = 1.5, 3.0
+    nu_V = ratio * (1 / s_nu - 0.5) / 3
+    rho, u = li.random_fields(4, 5, 3, seed=3, rho_lo=0.1, rho_hi=0.3)
+    if side == "liquid":
+        rho = rho + 1.0
+    cfg = dict(li.params(4, 5, 3, op=op, s_nu=s_nu), G=-1.0)
+    cfg.pop("tau_nu", None)
+    var = dict(cfg, nu_ratio=ratio, visc_rho_L=1.0, visc_rho_V=0.35)
+    const = dict(cfg, s_nu=1 / (3 * nu_V + 0.5) if side == "vapour" else s_nu)
+    pv, pc = ref.make_params(var), ref.make_params(const)
+    f0 = ref.equilibrium(pc, rho, u) * (1 + 0.02 * li.random_populations(4, 5, 3, 4, -1, 1))
+    a = ref.step(pv, f0, 1)
+    b = ref.step(pc, f0, 1)
+    assert np.allclose(a, b, rtol=1e-14, atol=0)
