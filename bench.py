@@ -244,7 +244,7 @@ def cpu_baseline(cfg, init, budget_s):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not implemented (--gpus must be 1)",
                           "n_gpus": a.gpus}))
         sys.exit(2)
     import torch

@@ -48,7 +48,7 @@ enum {
     LBM_ERR_BUFFER_TOO_SMALL = -2, /* workspace or buffer smaller than required */
     LBM_ERR_HIP = -3,              /* a HIP runtime call failed */
     LBM_ERR_NONFINITE = -4,        /* diagnostics found a NaN/Inf population */
-    LBM_ERR_UNSUPPORTED = -5       /* valid request this build does not implement */
+    LBM_ERR_UNSUPPORTED = -5       /* valid request the library does not implement */
 };
 
 /* Collision operator. */
