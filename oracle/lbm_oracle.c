@@ -68,6 +68,14 @@ typedef struct {
     int32_t nu_mask;                   /* bit k set: row k relaxes at s_nu */
     int32_t reserved2;
     double nu_ratio, visc_rho_L, visc_rho_V;
+    /* Single-phase runs (G = 0) may also have half-way bounce-back walls at
+     * x = -1/2, nx - 1/2 and y = -1/2, ny - 1/2 (the lid-driven cavity of
+     * Appendix B).  The face y = ny - 1/2 moves with velocity lid_u
+     * (tangential): a population reflected there gains
+     * -2 w_a lid_rho (e_a . lid_u) / c_s^2, a the direction that hit it. */
+    int32_t wall_x, wall_y;
+    double lid_u[3];
+    double lid_rho;
 } oracle_params;
 
 static int opp_of(int a) {
@@ -325,8 +333,13 @@ static void free_fields(fields_t *w) {
 static int check_params(const oracle_params *p) {
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return -1;
     if (p->wall_z && p->nz < 2) return -1;
+    if ((p->wall_x || p->wall_y) && p->G != 0.0) return -1;
     return 0;
 }
+
+/* Weight of direction a in the equilibrium's part linear in u: 1/18 axis,
+ * 1/36 diagonal (as in the rest state). */
+static double wlin(int a) { return a == 0 ? 1.0 / 3.0 : (a <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
 
 #ifdef _OPENMP
 #include <omp.h>
@@ -360,13 +373,22 @@ int oracle_step(const oracle_params *p, const double *fin, double *fout, int64_t
                     for (int a = 0; a < Q; ++a) fin_n[a] = cur[a * N + i];
                     collide_node(p, &w, x, y, z, fin_n, fo, NULL, NULL);
                     /* Eq. (5): streaming to x + e_a; half-way bounce-back when the
-                     * target lies beyond a wall. */
+                     * target lies beyond a wall, with the moving-lid term when
+                     * the wall crossed includes the face y = ny - 1/2. */
                     for (int a = 0; a < Q; ++a) {
-                        int64_t tz = z + EZ[a];
-                        if (p->wall_z && (tz < 0 || tz >= nz)) {
-                            fout[opp[a] * N + i] = fo[a];
+                        int64_t tx = x + EX[a], ty = y + EY[a], tz = z + EZ[a];
+                        int out_x = p->wall_x && (tx < 0 || tx >= nx);
+                        int out_y = p->wall_y && (ty < 0 || ty >= ny);
+                        int out_z = p->wall_z && (tz < 0 || tz >= nz);
+                        if (out_x || out_y || out_z) {
+                            double v = fo[a];
+                            if (p->wall_y && ty >= ny) {
+                                double eu = EX[a] * p->lid_u[0] + EY[a] * p->lid_u[1] + EZ[a] * p->lid_u[2];
+                                v -= 2.0 * wlin(a) * p->lid_rho * eu * 3.0;
+                            }
+                            fout[opp[a] * N + i] = v;
                         } else {
-                            int64_t t = (wrap(tz, nz) * ny + wrap(y + EY[a], ny)) * nx + wrap(x + EX[a], nx);
+                            int64_t t = (wrap(tz, nz) * ny + wrap(ty, ny)) * nx + wrap(tx, nx);
                             fout[a * N + t] = fo[a];
                         }
                     }

@@ -40,6 +40,8 @@ class OracleParams(ctypes.Structure):
         ("Minv", ctypes.c_double * (Q * Q)),
         ("nu_mask", ctypes.c_int32), ("reserved2", ctypes.c_int32),
         ("nu_ratio", ctypes.c_double), ("visc_rho_L", ctypes.c_double), ("visc_rho_V", ctypes.c_double),
+        ("wall_x", ctypes.c_int32), ("wall_y", ctypes.c_int32),
+        ("lid_u", ctypes.c_double * 3), ("lid_rho", ctypes.c_double),
     ]
 
 
@@ -131,6 +133,12 @@ def make_params(cfg: dict, nthreads: int = 0) -> OracleParams:
     p.nu_ratio = float(cfg.get("nu_ratio", 0.0))
     p.visc_rho_L = float(cfg.get("visc_rho_L", 0.0))
     p.visc_rho_V = float(cfg.get("visc_rho_V", 0.0))
+    p.wall_x = int(cfg.get("wall_x", 0))
+    p.wall_y = int(cfg.get("wall_y", 0))
+    lu = cfg.get("lid_u", (0.0, 0.0, 0.0))
+    for d in range(3):
+        p.lid_u[d] = float(lu[d])
+    p.lid_rho = float(cfg.get("lid_rho", 1.0))
     return p
 
 

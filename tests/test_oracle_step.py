@@ -374,3 +374,68 @@ def test_variable_viscosity_reduces_to_constant_rates_outside_range(op, side):
     a = ref.step(pv, f0, 1)
     b = ref.step(pc, f0, 1)
     assert np.allclose(a, b, rtol=1e-14, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# Single-phase walls on x and y and the moving lid (lid-driven cavity of
+# Appendix B)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("op", ["nonorth", "orth"])
+def test_plane_couette_flow_is_linear(op):
+    """Walls at y = -1/2 (fixed) and ny - 1/2 (moving at U along x): the
+    steady profile is u_x = U (y + 1/2) / ny, which half-way bounce-back
+    reproduces to rounding for the non-orthogonal model; the orthogonal
+    model's u^2 terms perturb the density at O(U^2) and the profile by
+    about 1e-7 U.  A wall misplaced by half a node would be off by ~3 %."""
+    ny, U = 16, 0.01
+    cfg = _single_phase(1, ny, 1, op, s_e=1.1, s_nu=1.0, wall_y=1, lid_u=(U, 0.0, 0.0))
+    p = ref.make_params(cfg)
+    f = ref.equilibrium(p, np.ones(ny), np.zeros((3, ny)))
+    f = ref.step(p, f, 20000)
+    fl = ref.fields(p, f)
+    y = np.arange(ny)
+    np.testing.assert_allclose(fl["u"][0], U * (y + 0.5) / ny, rtol=0, atol=(1e-9 if op == "nonorth" else 1e-6) * U)
+    np.testing.assert_allclose(fl["u"][1:], 0.0, atol=1e-12)
+
+
+def test_plane_couette_flow_reverses_with_the_lid():
+    """The sign of the lid term: a lid moving along -x drives -u_x."""
+    ny, U = 8, 0.01
+    cfg = _single_phase(1, ny, 1, "nonorth", s_e=1.1, s_nu=1.2, wall_y=1, lid_u=(-U, 0.0, 0.0))
+    p = ref.make_params(cfg)
+    f = ref.step(p, ref.equilibrium(p, np.ones(ny), np.zeros((3, ny))), 6000)
+    assert np.all(ref.fields(p, f)["u"][0] < 0)
+
+
+@pytest.mark.parametrize("op", ["nonorth", "orth"])
+def test_poiseuille_between_x_walls(op):
+    """Body force rho g_z between half-way walls at x = -1/2 and nx - 1/2:
+    g (x + 1/2)(nx - 1/2 - x) / (2 nu)."""
+    nx, gz, s_nu = 24, 1e-6, 1.0
+    cfg = _single_phase(nx, 1, 1, op, s_e=1.1, s_nu=s_nu, wall_x=1, gravity=(0.0, 0.0, gz))
+    p = ref.make_params(cfg)
+    f = ref.step(p, ref.equilibrium(p, np.ones(nx), np.zeros((3, nx))), 12000)
+    uz = ref.fields(p, f)["u"][2]
+    x = np.arange(nx)
+    nu = (1 / s_nu - 0.5) / 3
+    want = gz * (x + 0.5) * (nx - 0.5 - x) / (2 * nu)
+    assert np.abs(uz - want).max() < 0.01 * want.max()
+
+
+@pytest.mark.parametrize("op", ["nonorth", "orth"])
+def test_closed_cavity_conserves_mass_and_z_mirror_symmetry(op):
+    """Walls on all six faces, lid moving along x: mass is conserved (the lid
+    terms of opposite x-directions cancel) and the flow stays symmetric
+    under z -> nz - 1 - z."""
+    nx, ny, nz = 7, 6, 5
+    cfg = _single_phase(nx, ny, nz, op, s_e=1.1, s_nu=1.3, wall_x=1, wall_y=1, wall_z=1,
+                        lid_u=(0.05, 0.0, 0.0))
+    p = ref.make_params(cfg)
+    N = nx * ny * nz
+    f0 = ref.equilibrium(p, np.ones(N), np.zeros((3, N)))
+    f = ref.step(p, f0, 200)
+    assert abs(f.sum() - f0.sum()) < 1e-13 * f0.sum()
+    u = ref.fields(p, f)["u"].reshape(3, nz, ny, nx)
+    np.testing.assert_allclose(u[0], u[0][::-1], atol=1e-14)
+    np.testing.assert_allclose(u[2], -u[2][::-1], atol=1e-14)
+    assert u[0][:, -1, :].mean() > 0 > u[0][:, 0, :].mean()  # driven near the lid, return flow below
