@@ -98,6 +98,19 @@ typedef struct lbm_params {
      * its stress rows relax at 1 / (3 nu + 1/2).  nu_ratio must be >= 0 and
      * finite; when it is active, 0 <= visc_rho_V < visc_rho_L. */
     double nu_ratio, visc_rho_L, visc_rho_V;
+    /* Half-way bounce-back walls at x = -1/2, nx - 1/2 (wall_x = 1) and
+     * y = -1/2, ny - 1/2 (wall_y = 1), for single-phase runs only
+     * (psi_form = LBM_PSI_EXP with G = 0; else LBM_ERR_UNSUPPORTED): the
+     * lid-driven cavity of Appendix B.  The face y = ny - 1/2 moves with the
+     * tangential velocity lid_u (lid_u[1] must be 0; nonzero lid_u needs
+     * wall_y): a population reflected there gains
+     * -2 w_a lid_rho (e_a . lid_u) / c_s^2 (a the direction that hit the
+     * face, w = 1/18 axis, 1/36 diagonal), lid_rho > 0 when lid_u != 0.
+     * These runs use their own step kernel (one node per thread, no psi) in
+     * every step mode; batched runs must be periodic in x and y. */
+    int32_t wall_x, wall_y;
+    double lid_u[3];
+    double lid_rho;
 } lbm_params;
 
 /* Launch shape of the fused step: tx * ty threads per block, one thread per
@@ -171,7 +184,10 @@ lbm_status lbm_step(lbm_ctx *ctx, int64_t nsteps);
  * p = rho/3 + G psi^2/2 (N); device FP64 outputs, any may be NULL. */
 lbm_status lbm_read_fields(lbm_ctx *ctx, double *rho, double *u, double *p);
 
-/* Canonical populations fbar_a(x, t) (19 N device doubles) out / in. */
+/* Canonical populations fbar_a(x, t) (19 N device doubles) out / in.
+ * Storage rounds to the storage precision; with a moving lid the
+ * populations reflected off it are stored without the lid term and read
+ * back with it, so a round trip may differ there in the last bit. */
 lbm_status lbm_read_populations(lbm_ctx *ctx, double *f);
 lbm_status lbm_write_populations(lbm_ctx *ctx, const double *f);
 

@@ -39,6 +39,8 @@ class LbmParams(ctypes.Structure):
         ("gravity", ctypes.c_double * 3), ("theta_wall_deg", ctypes.c_double),
         ("ghost_rho_min", ctypes.c_double),
         ("nu_ratio", ctypes.c_double), ("visc_rho_L", ctypes.c_double), ("visc_rho_V", ctypes.c_double),
+        ("wall_x", ctypes.c_int32), ("wall_y", ctypes.c_int32),
+        ("lid_u", ctypes.c_double * 3), ("lid_rho", ctypes.c_double),
     ]
 
 
@@ -316,6 +318,12 @@ def make_params(cfg: dict) -> LbmParams:
     p.nu_ratio = cfg.get("nu_ratio", 0.0)
     p.visc_rho_L = cfg.get("visc_rho_L", 0.0)
     p.visc_rho_V = cfg.get("visc_rho_V", 0.0)
+    p.wall_x = int(cfg.get("wall_x", 0))
+    p.wall_y = int(cfg.get("wall_y", 0))
+    lu = cfg.get("lid_u", (0.0, 0.0, 0.0))
+    for d in range(3):
+        p.lid_u[d] = lu[d]
+    p.lid_rho = cfg.get("lid_rho", 1.0)
     return p
 
 

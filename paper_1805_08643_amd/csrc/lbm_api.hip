@@ -77,6 +77,18 @@ lbm_status validate(const lbm_params *p) {
             return fail(LBM_ERR_INVALID_ARG, "psi0, rho0 must be finite");
     }
     if (!std::isfinite(p->sigma)) return fail(LBM_ERR_INVALID_ARG, "sigma not finite");
+    if ((p->wall_x != 0 && p->wall_x != 1) || (p->wall_y != 0 && p->wall_y != 1))
+        return fail(LBM_ERR_INVALID_ARG, "wall_x and wall_y must be 0 or 1");
+    const bool lid = p->lid_u[0] != 0.0 || p->lid_u[1] != 0.0 || p->lid_u[2] != 0.0;
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(p->lid_u[d])) return fail(LBM_ERR_INVALID_ARG, "lid_u not finite");
+    if (lid && !p->wall_y) return fail(LBM_ERR_INVALID_ARG, "a moving lid needs wall_y = 1");
+    if (lid && p->lid_u[1] != 0.0) return fail(LBM_ERR_INVALID_ARG, "lid_u must be tangential (lid_u[1] = 0)");
+    if (lid && !(std::isfinite(p->lid_rho) && p->lid_rho > 0.0))
+        return fail(LBM_ERR_INVALID_ARG, "lid_rho must be positive");
+    if ((p->wall_x || p->wall_y) && !(p->psi_form == LBM_PSI_EXP && p->G == 0.0))
+        return fail(LBM_ERR_UNSUPPORTED, "walls on x or y are implemented for single-phase runs (exponential "
+                                         "psi with G = 0)");
     if (!(std::isfinite(p->nu_ratio) && p->nu_ratio >= 0.0))
         return fail(LBM_ERR_INVALID_ARG, "nu_ratio = %g must be finite and >= 0", p->nu_ratio);
     if (p->nu_ratio > 0.0 && p->nu_ratio != 1.0 &&
@@ -122,6 +134,7 @@ PhysD make_phys(const lbm_params &p) {
     d.h_exp = p.storage == LBM_STORE_F16S ? p.f16_exp : 0;
     d.psi_form = p.psi_form;
     // Density-dependent viscosity: nu = nuV + t dnu, t = (rho - vrhoV) vinv in [0, 1]
+    for (int k = 0; k < 3; ++k) d.lid6[k] = 6.0 * p.lid_rho * p.lid_u[k];
     d.visc = p.nu_ratio > 0.0 && p.nu_ratio != 1.0;
     if (d.visc) {
         const double nuL = (1.0 / p.s_nu - 0.5) / 3.0;
@@ -187,6 +200,8 @@ void fill_grid(GridDesc &g, const lbm_params &p, const lbm_tile &t) {
     g.ny = p.ny;
     g.nz = p.nz;
     g.wall = p.wall_z;
+    g.wall_x = p.wall_x;
+    g.wall_y = p.wall_y;
     g.N = (long long)p.nx * p.ny * p.nz;
     g.tx = t.tx;
     g.ty = t.ty;
@@ -235,7 +250,8 @@ lbm_tile pair_tile(int nx, int ny, int nz) {
     return t;
 }
 
-bool pairs_apply(const lbm_params &p) { return p.storage != ST_F64 && p.nx % 2 == 0; }
+bool box_walls(const lbm_params &p) { return p.wall_x || p.wall_y; }
+bool pairs_apply(const lbm_params &p) { return p.storage != ST_F64 && p.nx % 2 == 0 && !box_walls(p); }
 
 }  // namespace
 
@@ -319,6 +335,12 @@ lbm_status launch_step(lbm_ctx *c, const GridDesc &g, const void *src, void *dst
     return dispatch(c, [&](auto S, auto O, auto W) -> lbm_status {
         using T = typename Storage<S.value>::T;
         using R = typename Storage<S.value>::R;
+        if (box_walls(c->p)) {  // single phase with walls on x or y: own kernel
+            hipLaunchKernelGGL((k_single<S.value, O.value>), dim3(grid1d(g.N, 256, 1LL << 30)), dim3(256), 0,
+                               c->stream, (const T *)src, (T *)dst, g, c->pd);
+            HIP_TRY(hipGetLastError());
+            return LBM_OK;
+        }
         const unsigned grid = 8u * (unsigned)g.per_xcd;
         const int threads = block_threads(g.tx, g.ty, pairs);
         if constexpr (S.value != ST_F64) {
@@ -383,7 +405,7 @@ lbm_status one_step(lbm_ctx *c) {
     if (c->timing) {
         if ((s = timed_event(c, 2 * c->nev))) return s;
     }
-    if (c->mode == LBM_STEP_SLABS) {
+    if (c->mode == LBM_STEP_SLABS && !box_walls(c->p)) {
         if ((s = launch_slabs(c, c->state(), c->other()))) return s;
     } else if ((s = launch_step(c, c->g, c->state(), c->other(), c->mode == LBM_STEP_PAIRS))) {
         return s;
@@ -727,6 +749,7 @@ lbm_status lbm_set_step_mode(lbm_ctx *c, int32_t mode, int32_t slab_planes) {
     if (slab_planes < 1) return fail(LBM_ERR_INVALID_ARG, "slab_planes < 1");
     if (mode == LBM_STEP_PAIRS) {
         if (c->p.storage == ST_F64) return fail(LBM_ERR_UNSUPPORTED, "pair mode needs FP32 or F16S storage");
+        if (box_walls(c->p)) return fail(LBM_ERR_UNSUPPORTED, "runs with walls on x or y use their own kernel");
         if (c->p.nx % 2) return fail(LBM_ERR_UNSUPPORTED, "pair mode needs an even nx, got %d", c->p.nx);
         if (check_tile(c->tile, c->p.storage, true) != LBM_OK) {
             g_err.clear();
@@ -833,7 +856,8 @@ lbm_status batch_validate(const lbm_params *runs, int32_t n) {
     for (int k = 0; k < n; ++k) {
         lbm_status s = validate(&runs[k]);
         if (s) return fail(s, "run %d: %s", k, g_err.c_str());
-        if (runs[k].wall_z) return fail(LBM_ERR_UNSUPPORTED, "run %d: batched runs must be periodic", k);
+        if (runs[k].wall_z || runs[k].wall_x || runs[k].wall_y)
+            return fail(LBM_ERR_UNSUPPORTED, "run %d: batched runs must be periodic", k);
         if (runs[k].op != runs[0].op || runs[k].storage != runs[0].storage)
             return fail(LBM_ERR_INVALID_ARG, "run %d: all runs must share op and storage", k);
     }

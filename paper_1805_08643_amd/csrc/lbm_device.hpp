@@ -52,6 +52,7 @@ struct PhysD {  // host-filled, double
     int h_exp;  // F16S exponent offset: stored h = (fbar - w rho_ref) * 2^h_exp
     int visc;   // density-dependent viscosity on
     double nuV, dnu, vrhoV, vinv;
+    double lid6[3];  // 6 lid_rho lid_u: moving-face term of a reflected population
 };
 
 __device__ inline float r_rcp(float v);
@@ -69,6 +70,7 @@ template <class R> struct Phys {
     int psi_form;
     int visc;
     R nuV, dnu, vrhoV, vinv;
+    R lid6[3];
     __device__ inline void load(const PhysD &d) {
         G = (R)d.G;
         a = (R)d.a;
@@ -105,6 +107,9 @@ template <class R> struct Phys {
         dnu = (R)d.dnu;
         vrhoV = (R)d.vrhoV;
         vinv = (R)d.vinv;
+        lid6[0] = (R)d.lid6[0];
+        lid6[1] = (R)d.lid6[1];
+        lid6[2] = (R)d.lid6[2];
     }
     // Rate of the stress rows at a node of density rho: s_nu, or with a
     // density-dependent viscosity 1 / (3 nu + 1/2) with nu linear in rho
@@ -135,6 +140,10 @@ constexpr int kBufWord3 = 0x00020000;  // dword 3 of a raw buffer descriptor on 
 // non-temporal (measured slower on MI355X).
 #define LBM_BUF_AUX 0
 #endif
+#ifndef LBM_BUF_STORE_AUX
+// Cache policy of the buffer stores (same encoding).
+#define LBM_BUF_STORE_AUX LBM_BUF_AUX
+#endif
 __device__ inline rsrc_t make_rsrc(const void *base, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, kBufWord3);
 }
@@ -149,7 +158,7 @@ template <> struct Storage<ST_F64> {
     }
     __device__ static inline void stb(R v, rsrc_t r, uint32_t vo, uint32_t so, R, R) {
         using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, (int)vo, (int)so, LBM_BUF_AUX);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, (int)vo, (int)so, LBM_BUF_STORE_AUX);
     }
 };
 template <> struct Storage<ST_F32> {
@@ -161,7 +170,7 @@ template <> struct Storage<ST_F32> {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, LBM_BUF_AUX));
     }
     __device__ static inline void stb(R v, rsrc_t r, uint32_t vo, uint32_t so, R, R) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)vo, (int)so, LBM_BUF_AUX);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)vo, (int)so, LBM_BUF_STORE_AUX);
     }
 };
 // binary16 bits of h = (fbar - w rho_ref) * 2^e.  Loads return
@@ -184,7 +193,7 @@ template <> struct Storage<ST_F16S> {
     }
     __device__ static inline void stb(R v, rsrc_t r, uint32_t vo, uint32_t so, R shs, R hs) {
         __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(fmaf(v, hs, -shs))), r, (int)vo,
-                                              (int)so, LBM_BUF_AUX);
+                                              (int)so, LBM_BUF_STORE_AUX);
     }
 };
 

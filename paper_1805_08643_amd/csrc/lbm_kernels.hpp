@@ -23,11 +23,12 @@
 namespace lbm {
 
 struct GridDesc {
-    int nx, ny, nz, wall;
+    int nx, ny, nz, wall;  // wall: half-way bounce-back walls in z
     long long N;
     int tx, ty, cz;
     int ntx, nty, nzc;
     int ntiles, per_xcd;
+    int wall_x, wall_y;    // single-phase walls in x and y (moving lid on y = ny - 1/2)
 };
 
 __device__ inline int wrapi(int v, int n) {
@@ -143,10 +144,53 @@ __device__ inline void pull(const PopBuf &A, int nz, uint32_t PB, int z, const N
 #undef LBM_LD
 }
 
+// Where the population arriving at (x, y, z) in direction a is stored, with
+// walls on any axis: (idx, d) of A, and whether it reflected off the moving
+// face y = ny - 1/2 (then it carries lid_term(a) on top of the stored value).
+__device__ inline void box_source(const GridDesc &g, int x, int y, int z, int a, size_t &idx, int &d, bool &lid) {
+    int sx = x - ex(a), sy = y - ey(a), sz = z - ez(a);
+    const bool out = (g.wall_x && (sx < 0 || sx >= g.nx)) || (g.wall_y && (sy < 0 || sy >= g.ny)) ||
+                     (g.wall && (sz < 0 || sz >= g.nz));
+    lid = out && g.wall_y && sy >= g.ny;
+    if (out) {
+        idx = ((size_t)z * g.ny + y) * g.nx + x;
+        d = opp(a);
+    } else {
+        idx = ((size_t)wrapi(sz, g.nz) * g.ny + wrapi(sy, g.ny)) * g.nx + wrapi(sx, g.nx);
+        d = a;
+    }
+}
+
+// Moving-face term of a population arriving in direction a after reflection
+// off y = ny - 1/2: +2 w_a lid_rho (e_a . lid_u) / c_s^2 (the sign of the
+// term for the direction that hit the face is reversed, e_a = -e_hit).
+template <class R> __device__ inline R lid_term(const Phys<R> &P, int a) {
+    return (R)wclass(a) * ((R)ex(a) * P.lid6[0] + (R)ey(a) * P.lid6[1] + (R)ez(a) * P.lid6[2]);
+}
+
+template <int S>
+__device__ inline void pull_box(const typename Storage<S>::T *__restrict__ A, const GridDesc &g, int x, int y,
+                                int z, const Phys<typename Storage<S>::R> &P, typename Storage<S>::R f[Q]) {
+    using ST = Storage<S>;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+        size_t idx;
+        int d;
+        bool lid;
+        box_source(g, x, y, z, a, idx, d, lid);
+        f[a] = ST::load(A + (size_t)d * g.N + idx, P.sh(a), P.hsi);
+        if (lid) f[a] += lid_term(P, a);
+    }
+}
+
 // Pull at an arbitrary node (readback and diagnostics kernels).
 template <int S, bool WALL>
 __device__ inline void pull_at(const typename Storage<S>::T *__restrict__ A, const GridDesc &g, int x, int y, int z,
                                const Phys<typename Storage<S>::R> &P, typename Storage<S>::R f[Q]) {
+    if (g.wall_x | g.wall_y) {
+        pull_box<S>(A, g, x, y, z, P, f);
+        return;
+    }
     NbOff o;
     o.set(x, wrapi(x - 1, g.nx), wrapi(x + 1, g.nx), y, wrapi(y - 1, g.ny), wrapi(y + 1, g.ny), g.nx,
           (uint32_t)sizeof(typename Storage<S>::T));
@@ -375,7 +419,7 @@ template <> struct Wide<ST_F32> {
     __device__ static inline void st2(float a, float b, rsrc_t r, uint32_t vo, uint32_t so, float, float) {
         using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
         const W w = (W)__float_as_uint(a) | ((W)__float_as_uint(b) << 32);
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, w), r, (int)vo, (int)so, LBM_BUF_AUX);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, w), r, (int)vo, (int)so, LBM_BUF_STORE_AUX);
     }
 };
 template <> struct Wide<ST_F16S> {
@@ -395,7 +439,7 @@ template <> struct Wide<ST_F16S> {
     __device__ static inline void st2(float a, float b, rsrc_t r, uint32_t vo, uint32_t so, float shs, float hs) {
         const uint32_t ha = __half_as_ushort(__float2half_rn(fmaf(a, hs, -shs)));
         const uint32_t hb = __half_as_ushort(__float2half_rn(fmaf(b, hs, -shs)));
-        __builtin_amdgcn_raw_buffer_store_b32(ha | (hb << 16), r, (int)vo, (int)so, LBM_BUF_AUX);
+        __builtin_amdgcn_raw_buffer_store_b32(ha | (hb << 16), r, (int)vo, (int)so, LBM_BUF_STORE_AUX);
     }
 };
 
@@ -683,6 +727,32 @@ __global__ void LBM_STEP_ATTR
 }
 
 // ---------------------------------------------------------------------------
+// Single-phase step with walls on any axis (the lid-driven cavity of
+// Appendix B): no pseudopotential, one node per thread; the body force is
+// rho g.  Reads through box_source, writes at the node itself.
+// ---------------------------------------------------------------------------
+template <int S, int OP>
+__global__ void __launch_bounds__(256)
+    k_single(const typename Storage<S>::T *__restrict__ A, typename Storage<S>::T *__restrict__ B, GridDesc g,
+             PhysD pd) {
+    using ST = Storage<S>;
+    using R = typename ST::R;
+    Phys<R> P;
+    P.load(pd);
+    const int nx = g.nx, ny = g.ny;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < g.N;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((long long)nx * ny));
+        R f[Q];
+        pull_box<S>(A, g, x, y, z, P, f);
+        const R rho = sum19<R>(f);
+        collide<R, OP>(f, rho, rho * P.gx, rho * P.gy, rho * P.gz, (R)0, P);
+#pragma unroll
+        for (int a = 0; a < Q; ++a) ST::store(B + (size_t)a * g.N + i, f[a], P.shh(a), P.hs);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Batched independent periodic runs.  One persistent launch per time step:
 // every block walks a work list of (run, tile) items; item -> run by binary
 // search over the runs' first-item indices.  Items are dealt so that each
@@ -967,6 +1037,17 @@ __device__ inline void scatter_node(typename Storage<S>::T *__restrict__ A, cons
                                     const Phys<typename Storage<S>::R> &P, int x, int y, int z,
                                     const typename Storage<S>::R v[Q]) {
     using ST = Storage<S>;
+    if (g.wall_x | g.wall_y) {
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            size_t idx;
+            int d;
+            bool lid;
+            box_source(g, x, y, z, a, idx, d, lid);
+            ST::store(A + (size_t)d * g.N + idx, lid ? v[a] - lid_term(P, a) : v[a], P.shh(d), P.hs);
+        }
+        return;
+    }
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
         int sz = z - ez(a);
