@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-workloads", action="store_true",
+                    help="only time the oracle on the host for every standard workload (one JSON line each)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (HBM counter calibration)")
     return ap.parse_args()
@@ -241,8 +243,62 @@ def cpu_baseline(cfg, init, budget_s):
             "single_thread_mlups": round(st1, 3), "single_thread_sample": "64^3 droplet, 2 steps, 1 thread"}
 
 
+def host_cpu():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline_workloads(threads=16):
+    """The oracle's rate (MLUPS, FP64) on the host for each standard
+    workload: a few steps each, since the rate is per lattice update; the
+    batch is sampled by one step of each of its first 32 runs; one more
+    figure with a single thread on the 128^3 lattice."""
+    import lbm_inputs as li
+    from oracle import ref
+    threads = min(threads, os.cpu_count() or 1)
+    work = [("droplet_32", li.c1_droplet, 200), ("laplace_128", lambda: li.c2_laplace(24), 10),
+            ("two_droplets_256", li.c3_two_droplets, 3), ("sessile_384x384x192", lambda: li.c4_sessile(60.0), 2)]
+    out = []
+    for name, fn, steps in work:
+        cfg, init = fn()
+        p = ref.make_params(cfg, nthreads=threads)
+        f = ref.equilibrium(p, *li.init_fields(cfg, init))
+        t0 = time.perf_counter()
+        f = ref.step(p, f, steps)
+        n = cfg["nx"] * cfg["ny"] * cfg["nz"]
+        out.append({"workload": name, "nodes": n, "oracle_mlups": round(n * steps / (time.perf_counter() - t0) / 1e6, 2),
+                    "threads": threads, "steps": steps})
+        del f
+    t0 = time.perf_counter()
+    done = 0
+    for pp, init in li.c5_batch()[:32]:
+        pr = ref.make_params(pp, nthreads=threads)
+        ref.step(pr, ref.equilibrium(pr, *li.init_fields(pp, init)), 1)
+        done += pp["nx"] * pp["ny"] * pp["nz"]
+    out.append({"workload": "batch_256_runs", "oracle_mlups": round(done / (time.perf_counter() - t0) / 1e6, 2),
+                "threads": threads, "sample": "1 step of each of the first 32 runs"})
+    cfg, init = li.c2_laplace(24)
+    p = ref.make_params(cfg, nthreads=1)
+    f = ref.equilibrium(p, *li.init_fields(cfg, init))
+    t0 = time.perf_counter()
+    ref.step(p, f, 2)
+    out.append({"workload": "laplace_128", "oracle_mlups": round(128 ** 3 * 2 / (time.perf_counter() - t0) / 1e6, 3),
+                "threads": 1, "steps": 2, "host_cpu": host_cpu(), "logical_cpus": os.cpu_count()})
+    return out
+
+
 def main():
     a = parse()
+    if a.cpu_workloads:
+        for row in cpu_baseline_workloads():
+            print(json.dumps(row), flush=True)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not implemented (--gpus must be 1)",
                           "n_gpus": a.gpus}))

@@ -11,7 +11,7 @@ vapour coexistence densities; several droplets combine by taking, at each
 node, the droplet whose profile is largest.  The velocity of a droplet is
 scaled by its liquid fraction (rho - rho_V) / (rho_L - rho_V).  Coexistence
 densities come from ``coexistence.json`` (Maxwell construction, written by
-``make_coexistence.py``), interpolated linearly in T/T_c.
+``oracle/make_coexistence.py``), interpolated linearly in T/T_c.
 """
 from __future__ import annotations
 

@@ -1,8 +1,8 @@
-"""Write ``coexistence.json``: Maxwell coexistence densities of the
+"""Write ``lbm_inputs/coexistence.json``: Maxwell coexistence densities of the
 Carnahan-Starling EOS (b = 4, R = 1; the values do not depend on a) on a grid
 of reduced temperatures, and of the exponential pseudopotential with
 psi0 = rho0 = 1, G = -10/3.  Calls only the oracle.  Run from the repo root:
-    python lbm_inputs/make_coexistence.py
+    python oracle/make_coexistence.py
 """
 import json
 import os
@@ -29,7 +29,7 @@ def main():
                      "p = rho/3 + G psi^2/2 (oracle/eos.py)",
            "carnahan_starling_b4_R1": {"columns": ["T_over_Tc", "rho_L", "rho_V"], "rows": table},
            "exponential_G-10/3": {"rho_L": rl, "rho_V": rv}}
-    with open(os.path.join(HERE, "coexistence.json"), "w") as fh:
+    with open(os.path.join(os.path.dirname(HERE), "lbm_inputs", "coexistence.json"), "w") as fh:
         json.dump(out, fh, indent=1)
 
 

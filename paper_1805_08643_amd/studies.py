@@ -32,7 +32,7 @@ returns plain dicts (one line of JSON per run is printed as it finishes).
              r0 in 12..28, FP64 and FP32 storage, both operators.
   contact_cs Sessile droplet with the C-S EOS at T = 0.7 T_c on
              384 x 384 x 192, gravity 1e-6 along -z, 60 / 90 / 120 deg, FP32.
-  throughput GPU and oracle MLUPS for each standard workload.
+  throughput GPU MLUPS for each standard workload.
   precision  FP32 and shifted-FP16 storage against FP64 storage on the 256^3
              two-droplet run (steps 100, 500, 1000, 2000).
 
@@ -466,26 +466,23 @@ def cavity_mach(L=80, Re=400.0, speeds=(0.1, 0.3, 0.5), transits=60, storage="f6
     return out
 
 
-def throughput(steps=None, cpu_threads=16):
-    """MLUPS of the GPU path and of the FP64 oracle on the host for each
-    standard workload: 32^3 droplet (FP64), 128^3 Laplace droplet (FP64,
-    FP32), 256^3 two droplets (FP64, FP32, F16S), 384 x 384 x 192 sessile
-    droplet (FP32), and the 256-run batch (FP32, F16S).  The oracle runs a
-    few steps per workload (its rate does not depend on the step count),
-    with `cpu_threads` threads and once with one thread."""
+def throughput():
+    """GPU MLUPS for each standard workload: 32^3 droplet (FP64), 128^3
+    Laplace droplet (FP64, FP32), 256^3 two droplets (FP64, FP32, F16S),
+    384 x 384 x 192 sessile droplet (FP32), and the 256-run batch (FP32,
+    F16S), with the kernels and tiles of ``tuning``.  (The oracle's rates on
+    the host for the same workloads come from ``bench.py --cpu-workloads``.)"""
     import torch
 
     import lbm_inputs as li
-    from oracle import ref
     from paper_1805_08643_amd import tuning
     from paper_1805_08643_amd.binding import Batch, f16_exp_for
-    threads = min(cpu_threads, os.cpu_count() or 1)
-    work = [("droplet_32", li.c1_droplet, ("f64",), 500, 200),
-            ("laplace_128", lambda: li.c2_laplace(24), ("f64", "f32"), 200, 10),
-            ("two_droplets_256", li.c3_two_droplets, ("f64", "f32", "f16s"), 200, 3),
-            ("sessile_384x384x192", lambda: li.c4_sessile(60.0), ("f32",), 200, 2)]
+    work = [("droplet_32", li.c1_droplet, ("f64",), 500),
+            ("laplace_128", lambda: li.c2_laplace(24), ("f64", "f32"), 200),
+            ("two_droplets_256", li.c3_two_droplets, ("f64", "f32", "f16s"), 200),
+            ("sessile_384x384x192", lambda: li.c4_sessile(60.0), ("f32",), 200)]
     out = []
-    for name, fn, storages, gsteps, csteps in work:
+    for name, fn, storages, gsteps in work:
         cfg, init = fn()
         row = dict(study="throughput", workload=name, nodes=cfg["nx"] * cfg["ny"] * cfg["nz"])
         for st in storages:
@@ -506,16 +503,7 @@ def throughput(steps=None, cpu_threads=16):
             torch.cuda.synchronize()
             row[f"gpu_{st}_mlups"] = round(row["nodes"] * gsteps / (e0.elapsed_time(e1) * 1e-3) / 1e6, 1)
             lat.close()
-        p = ref.make_params(cfg, nthreads=threads)
-        f = ref.equilibrium(p, *li.init_fields(cfg, init))
-        t0 = time.perf_counter()
-        f = ref.step(p, f, csteps)
-        row["oracle_mlups"] = round(row["nodes"] * csteps / (time.perf_counter() - t0) / 1e6, 2)
-        row["oracle_threads"] = threads
-        row["oracle_steps"] = csteps
-        del f
         out.append(_emit(row))
-    # batched runs
     runs = li.c5_batch()
     row = dict(study="throughput", workload="batch_256_runs")
     for st in ("f32", "f16s"):
@@ -537,38 +525,8 @@ def throughput(steps=None, cpu_threads=16):
         b.close()
         del b
         torch.cuda.empty_cache()
-    t0 = time.perf_counter()
-    done = 0
-    for pp, init in runs[:32]:
-        pr = ref.make_params(pp, nthreads=threads)
-        f = ref.equilibrium(pr, *li.init_fields(pp, init))
-        ref.step(pr, f, 1)
-        done += pp["nx"] * pp["ny"] * pp["nz"]
-    row["oracle_mlups"] = round(done / (time.perf_counter() - t0) / 1e6, 2)
-    row["oracle_threads"] = threads
-    row["oracle_sample"] = "1 step of each of the first 32 runs"
     out.append(_emit(row))
-    # one thread, on the 128^3 lattice
-    cfg, init = li.c2_laplace(24)
-    p = ref.make_params(cfg, nthreads=1)
-    f = ref.equilibrium(p, *li.init_fields(cfg, init))
-    t0 = time.perf_counter()
-    ref.step(p, f, 2)
-    out.append(_emit(dict(study="throughput", workload="laplace_128", oracle_threads=1, oracle_steps=2,
-                          oracle_mlups=round(128 ** 3 * 2 / (time.perf_counter() - t0) / 1e6, 3),
-                          host_cpu=_host_cpu())))
     return out
-
-
-def _host_cpu():
-    try:
-        with open("/proc/cpuinfo") as fh:
-            for line in fh:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip() + f" ({os.cpu_count()} logical CPUs visible)"
-    except OSError:
-        pass
-    return None
 
 
 def laplace_cs(ops=("nonorth", "orth"), storages=("f64", "f32"), radii=(24, 28, 32, 36, 40), steps=20000):
