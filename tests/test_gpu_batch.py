@@ -114,3 +114,24 @@ def test_batch_full_workload_sampled_runs():
         print(f"  run {k} L={p['nx']}: err {e:.3e}")
         assert e < 1.5e-5
     b.close()
+
+
+def test_batch_variable_viscosity_matches_single_lattices():
+    """Per-run parameters travel through the batch descriptor, including the
+    density-dependent viscosity."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    runs = _runs("f32", sizes=(24, 32, 20))
+    cfgs = []
+    for k, (p, init) in enumerate(runs):
+        cfgs.append(dict(p, nu_ratio=float(2 + 3 * k), visc_rho_L=init["rho_L"], visc_rho_V=init["rho_V"]))
+    b = Batch(cfgs)
+    for k, (p, init) in enumerate(runs):
+        b.init_fields(k, *li.init_fields(cfgs[k], init))
+    b.step(4, 2)
+    for k, (p, init) in enumerate(runs):
+        lat = Lattice(cfgs[k])
+        lat.init_fields(*li.init_fields(cfgs[k], init)).step(4)
+        assert np.array_equal(b.pops(k), lat.read_populations().cpu().numpy()), k
+        lat.close()
+    b.close()

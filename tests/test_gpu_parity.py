@@ -545,3 +545,18 @@ def test_cavity_rejections():
     with pytest.raises(binding.LbmError) as e:
         binding.Batch([cfg])
     assert e.value.status == -5
+
+
+def test_diagnostics_are_deterministic():
+    """The two-pass FP64 reduction has a fixed order: repeated calls on the
+    same state give the same bits."""
+    cfg, rho, u, tile = _case("ragged_70x37x21", "nonorth", "f32")
+    _need_gpu()
+    lat = Lattice(cfg)
+    lat.init_fields(rho, u).step(3)
+    c = (35.0, 18.5, 10.0)
+    d1 = lat.diagnostics(center=c, r_in=5.0, r_out=15.0)
+    d2 = lat.diagnostics(center=c, r_in=5.0, r_out=15.0)
+    lat.close()
+    for k in ("mass", "momentum", "max_u", "p_in", "p_out", "rho_in", "rho_out", "n_in", "n_out"):
+        assert d1[k] == d2[k], k
