@@ -256,6 +256,18 @@ lbm_status lbm_batch_init_fields(lbm_batch *b, int32_t run, const double *rho, c
 lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps, int32_t graph_steps);
 lbm_status lbm_batch_read_fields(lbm_batch *b, int32_t run, double *rho, double *u, double *p);
 lbm_status lbm_batch_read_populations(lbm_batch *b, int32_t run, double *f);
+/* Diagnostics of run `run`, as lbm_diagnostics gives them for a single
+ * lattice (Sec. IV.B sums; FP64, fixed order); synchronises the stream.
+ * LBM_ERR_NONFINITE (out still filled) if that run holds NaN or Inf. */
+lbm_status lbm_batch_diagnostics(lbm_batch *b, int32_t run, const lbm_diag_request *req, lbm_diag *out);
+/* Status of every run: status[k] = LBM_OK, or LBM_ERR_NONFINITE when the
+ * populations of run k hold NaN or Inf.  status: host array of
+ * lbm_batch_runs(b) entries, owned by the caller.  Returns LBM_OK when all
+ * runs are finite, LBM_ERR_NONFINITE (message names the first such run)
+ * otherwise, or the first HIP error.  Synchronises the stream. */
+lbm_status lbm_batch_status(lbm_batch *b, lbm_status *status);
+/* Number of runs in the batch (0 for NULL). */
+int32_t lbm_batch_runs(const lbm_batch *b);
 /* Persistent grid size (blocks), per-run tiles and step kernel (one or two
  * nodes per thread, where both apply) chosen by timing candidates;
  * synchronises; state unchanged. */

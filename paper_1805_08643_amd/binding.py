@@ -118,6 +118,9 @@ SIGNATURES = {
     "lbm_batch_get_step_mode": (_i32, [_vp, _P(_i32)]),
     "lbm_batch_kernel_time": (_i32, [_vp, _dp, _P(_i64)]),
     "lbm_batch_nodes": (_i64, [_vp]),
+    "lbm_batch_diagnostics": (_i32, [_vp, _i32, _P(LbmDiagRequest), _P(LbmDiag)]),
+    "lbm_batch_status": (_i32, [_vp, _P(_i32)]),
+    "lbm_batch_runs": (_i32, [_vp]),
 }
 
 _lib = None
@@ -204,6 +207,22 @@ def lbm_diagnostics(ctx, req: LbmDiagRequest | None) -> tuple[int, LbmDiag]:
     if st not in (0, -4):
         check(st, "lbm_diagnostics")
     return st, d
+
+
+def _diag_request(center, r_in, r_out):
+    if center is None:
+        return None
+    req = LbmDiagRequest()
+    for a in range(3):
+        req.center[a] = float(center[a])
+    req.r_in, req.r_out = float(r_in), float(r_out)
+    return req
+
+
+def _diag_dict(st, d):
+    return {"status": st, "mass": d.mass, "momentum": tuple(d.momentum), "max_u": d.max_u,
+            "p_in": d.p_in, "p_out": d.p_out, "rho_in": d.rho_in, "rho_out": d.rho_out,
+            "n_in": d.n_in, "n_out": d.n_out, "nonfinite": d.nonfinite, "step": d.step}
 
 
 def lbm_state_bytes(ctx) -> int:
@@ -402,16 +421,8 @@ class Lattice:
         return self
 
     def diagnostics(self, center=None, r_in=0.0, r_out=0.0):
-        req = None
-        if center is not None:
-            req = LbmDiagRequest()
-            for a in range(3):
-                req.center[a] = float(center[a])
-            req.r_in, req.r_out = float(r_in), float(r_out)
-        st, d = lbm_diagnostics(self.ctx, req)
-        return {"status": st, "mass": d.mass, "momentum": tuple(d.momentum), "max_u": d.max_u,
-                "p_in": d.p_in, "p_out": d.p_out, "rho_in": d.rho_in, "rho_out": d.rho_out,
-                "n_in": d.n_in, "n_out": d.n_out, "nonfinite": d.nonfinite, "step": d.step}
+        st, d = lbm_diagnostics(self.ctx, _diag_request(center, r_in, r_out))
+        return _diag_dict(st, d)
 
     def save_state(self):
         torch = _torch()
@@ -509,6 +520,29 @@ class Batch:
         p = torch.empty(N, dtype=torch.float64, device=self.device)
         _call("lbm_batch_read_fields", _vp(self.h), run, _vp(rho.data_ptr()), _vp(u.data_ptr()), _vp(p.data_ptr()))
         return {"rho": rho, "u": u, "p": p}
+
+    def diagnostics(self, run, center=None, r_in=0.0, r_out=0.0):
+        """Diagnostics of one run, as Lattice.diagnostics gives them."""
+        req = _diag_request(center, r_in, r_out)
+        d = LbmDiag()
+        st = lib().lbm_batch_diagnostics(_vp(self.h), int(run), ctypes.byref(req) if req is not None else None,
+                                         ctypes.byref(d))
+        if st not in (0, -4):
+            check(st, "lbm_batch_diagnostics")
+        return _diag_dict(st, d)
+
+    def status(self):
+        """Per-run status codes (0 ok, -4 non-finite populations)."""
+        n = lib().lbm_batch_runs(_vp(self.h))
+        arr = (_i32 * n)()
+        st = lib().lbm_batch_status(_vp(self.h), arr)
+        if st not in (0, -4):
+            check(st, "lbm_batch_status")
+        return [int(v) for v in arr]
+
+    @property
+    def runs(self):
+        return lib().lbm_batch_runs(_vp(self.h))
 
     def autotune(self, trials=3):
         b = _i32(0)

@@ -1106,6 +1106,37 @@ lbm_status lbm_batch_read_populations(lbm_batch *b, int32_t run, double *f) {
     return lbm_read_populations(c, f);
 }
 
+lbm_status lbm_batch_diagnostics(lbm_batch *b, int32_t run, const lbm_diag_request *req, lbm_diag *out) {
+    lbm_ctx *c = nullptr;
+    lbm_status s = batch_run(b, &c, run);
+    if (s) return s;
+    s = lbm_diagnostics(c, req, out);
+    if (s == LBM_ERR_NONFINITE) return fail(s, "run %d: %s", run, g_err.c_str());
+    return s;
+}
+
+lbm_status lbm_batch_status(lbm_batch *b, lbm_status *status) {
+    if (!b || !status) return fail(LBM_ERR_INVALID_ARG, "null argument");
+    int first = -1;
+    int64_t first_bad = 0;
+    for (size_t k = 0; k < b->runs.size(); ++k) {
+        lbm_diag d{};
+        const lbm_status s = lbm_diagnostics(b->runs[k], nullptr, &d);
+        if (s != LBM_OK && s != LBM_ERR_NONFINITE) return s;
+        status[k] = s;
+        if (s == LBM_ERR_NONFINITE && first < 0) {
+            first = (int)k;
+            first_bad = d.nonfinite;
+        }
+    }
+    if (first >= 0)
+        return fail(LBM_ERR_NONFINITE, "run %d: %lld non-finite populations at step %lld", first,
+                    (long long)first_bad, (long long)b->runs[first]->steps);
+    return LBM_OK;
+}
+
+int32_t lbm_batch_runs(const lbm_batch *b) { return b ? (int32_t)b->runs.size() : 0; }
+
 lbm_status lbm_batch_set_blocks(lbm_batch *b, int32_t blocks) {
     if (!b) return fail(LBM_ERR_INVALID_ARG, "batch is NULL");
     if (blocks < 1) return fail(LBM_ERR_INVALID_ARG, "blocks < 1");

@@ -135,3 +135,38 @@ def test_batch_variable_viscosity_matches_single_lattices():
         assert np.array_equal(b.pops(k), lat.read_populations().cpu().numpy()), k
         lat.close()
     b.close()
+
+
+def test_batch_diagnostics_and_status_per_run():
+    """Per-run diagnostics equal those of the same lattice run alone (same
+    populations, same fixed-order reduction), and a run whose populations are
+    not finite is flagged alone.  The NaN is planted in that run's initial
+    density from the host; NaN arithmetic raises nothing on the device."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    runs = _runs("f32", sizes=(20, 24, 16))
+    b = Batch([r[0] for r in runs])
+    fields = [li.init_fields(p, i) for p, i in runs]
+    rho_bad = np.array(fields[1][0], copy=True)
+    rho_bad.reshape(-1)[7] = np.nan
+    print(f"[gpu] batch status runs={[r[0]['nx'] for r in runs]} nan in run 1", flush=True)
+    for k, (rho, u) in enumerate(fields):
+        b.init_fields(k, rho_bad if k == 1 else rho, u)
+    b.step(3, 0)
+    assert b.runs == 3
+    assert b.status() == [0, -4, 0]
+    for k in (0, 2):
+        p, init = runs[k]
+        lat = Lattice(p)
+        lat.init_fields(*fields[k]).step(3)
+        c = (p["nx"] / 2, p["ny"] / 2, p["nz"] / 2)
+        want = lat.diagnostics(c, 3.0, 7.0)
+        got = b.diagnostics(k, c, 3.0, 7.0)
+        lat.close()
+        assert got["status"] == 0 and got["nonfinite"] == 0 and got["step"] == 3
+        for key in ("mass", "momentum", "max_u", "p_in", "p_out", "rho_in", "rho_out", "n_in", "n_out"):
+            assert got[key] == want[key], key
+    bad = b.diagnostics(1)
+    assert bad["status"] == -4 and bad["nonfinite"] > 0
+    assert "run 1" in binding.lbm_last_error()
+    b.close()
