@@ -233,6 +233,15 @@ lbm_status lbm_get_step_mode(const lbm_ctx *ctx, int32_t *mode, int32_t *slab_pl
  * since the last call, measured with HIP events on the context's stream when
  * timing is enabled (lbm_set_timing(ctx, 1)).  Synchronises. */
 lbm_status lbm_set_timing(lbm_ctx *ctx, int32_t enable);
+
+/* Write check, a debug aid for the streaming of Eq. (5): each step must
+ * write all 19 populations of every node.  With enable != 0, every step first
+ * fills the destination population buffer with all-ones bits (NaN in FP64,
+ * FP32 and F16S storage).  A node the step fails to write then shows up as
+ * non-finite in lbm_diagnostics and in the populations.  Costs one extra
+ * write pass per step, outside the timed region of lbm_set_timing; kernels
+ * only, so a captured step stays capturable. */
+lbm_status lbm_set_write_check(lbm_ctx *ctx, int32_t enable);
 lbm_status lbm_kernel_time(lbm_ctx *ctx, double *avg_ms, int64_t *launches);
 
 int64_t lbm_step_count(const lbm_ctx *ctx);

@@ -118,6 +118,7 @@ SIGNATURES = {
     "lbm_batch_get_step_mode": (_i32, [_vp, _P(_i32)]),
     "lbm_batch_kernel_time": (_i32, [_vp, _dp, _P(_i64)]),
     "lbm_batch_nodes": (_i64, [_vp]),
+    "lbm_set_write_check": (_i32, [_vp, _i32]),
     "lbm_batch_diagnostics": (_i32, [_vp, _i32, _P(LbmDiagRequest), _P(LbmDiag)]),
     "lbm_batch_status": (_i32, [_vp, _P(_i32)]),
     "lbm_batch_runs": (_i32, [_vp]),
@@ -437,6 +438,11 @@ class Lattice:
 
     def set_tile(self, tx, ty, cz):
         lbm_set_tile(self.ctx, tx, ty, cz)
+
+    def set_write_check(self, on=True):
+        """Fill the destination buffer with NaN before every step (debug)."""
+        _call("lbm_set_write_check", _vp(self.ctx), int(bool(on)))
+        return self
 
     def get_tile(self):
         return lbm_get_tile(self.ctx)

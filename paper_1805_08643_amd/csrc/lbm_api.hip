@@ -273,6 +273,7 @@ struct lbm_ctx {
     size_t nev = 0;              // pairs recorded since last read
     int mode = LBM_STEP_FUSED;
     int slab = 32;
+    bool write_check = false;
 
     void *state() const { return ws + (cur ? L.B : L.A); }
     void *other() const { return ws + (cur ? L.A : L.B); }
@@ -399,9 +400,20 @@ lbm_status timed_event(lbm_ctx *c, size_t k) {
     return LBM_OK;
 }
 
+// All-ones bits over n 16-bit words: NaN in every storage format.
+__global__ void __launch_bounds__(256) k_fill_ones(uint16_t *p, long long n) {
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) p[i] = 0xFFFFu;
+}
+
 lbm_status one_step(lbm_ctx *c) {
     lbm_status s = launch_walls(c, c->state());
     if (s) return s;
+    if (c->write_check) {
+        const long long words = 19LL * c->g.N * (long long)elem_bytes(c->p.storage) / 2;
+        hipLaunchKernelGGL(k_fill_ones, dim3(grid1d(words, 256)), dim3(256), 0, c->stream,
+                           (uint16_t *)c->other(), words);
+        HIP_TRY(hipGetLastError());
+    }
     if (c->timing) {
         if ((s = timed_event(c, 2 * c->nev))) return s;
     }
@@ -766,6 +778,12 @@ lbm_status lbm_get_step_mode(const lbm_ctx *c, int32_t *mode, int32_t *slab_plan
     if (!c || !mode) return fail(LBM_ERR_INVALID_ARG, "null argument");
     *mode = c->mode;
     if (slab_planes) *slab_planes = c->slab;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_write_check(lbm_ctx *c, int32_t enable) {
+    if (!c) return fail(LBM_ERR_INVALID_ARG, "ctx is NULL");
+    c->write_check = enable != 0;
     return LBM_OK;
 }
 

@@ -560,3 +560,42 @@ def test_diagnostics_are_deterministic():
     lat.close()
     for k in ("mass", "momentum", "max_u", "p_in", "p_out", "rho_in", "rho_out", "n_in", "n_out"):
         assert d1[k] == d2[k], k
+
+
+# ---------------------------------------------------------------------------
+# Write check: the destination buffer is filled with NaN before every step,
+# so any node a step kernel leaves unwritten would surface as non-finite and
+# break bit identity with the unchecked run.
+# ---------------------------------------------------------------------------
+WRITE_CHECK_CASES = [("ragged_70x37x21", "f32", "fused", None), ("ragged_70x37x21", "f16s", "pairs", (32, 4, 7)),
+                     ("walls_40x33x19_60deg", "f64", "fused", None),
+                     ("walls_40x33x19_60deg", "f32", "pairs", (16, 8, 7)),
+                     ("walls_37x20x12_120deg", "f32", "slabs", None), ("cavity", "f32", "fused", None)]
+
+
+@pytest.mark.parametrize("name,storage,mode,tile", WRITE_CHECK_CASES)
+def test_every_node_written_each_step(name, storage, mode, tile):
+    _need_gpu()
+    if name == "cavity":
+        cfg, rho, u = _cavity(14, 11, 9, "nonorth", storage)
+    else:
+        cfg, rho, u, ctile = _case(name, "nonorth", storage)
+        tile = tile or ctile
+    print(f"[gpu] write check {name} {storage} {mode} tile={tile}", flush=True)
+    out = []
+    for check in (False, True):
+        lat = Lattice(cfg)
+        if mode == "slabs":
+            lat.set_step_mode("slabs", 5)
+        elif mode == "pairs":
+            lat.set_step_mode("pairs")
+        if tile is not None:
+            lat.set_tile(*tile)
+        lat.set_write_check(check)
+        lat.init_fields(rho, u).step(3)
+        d = lat.diagnostics()
+        assert d["status"] == 0 and d["nonfinite"] == 0
+        out.append(lat.read_populations().cpu().numpy())
+        lat.close()
+    assert np.isfinite(out[1]).all()
+    assert np.array_equal(out[0], out[1])
