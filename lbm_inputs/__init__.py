@@ -148,6 +148,19 @@ def c4_sessile(theta_deg=60.0, nx=384, ny=384, nz=192, r0=40.0):
     return p, init
 
 
+def cold_droplet(s_nu, n=16, T_over_Tc=0.5, r0=5.0, storage="f64"):
+    """Droplet at T = 0.5 T_c (Maxwell density ratio about 724) with a given
+    stress rate s_nu: the large-density-ratio regime where too small a
+    viscosity destabilises the scheme (Sec. IV.A)."""
+    a, W = interface_recipe(T_over_Tc)
+    p = params(n, n, n, T_over_Tc=T_over_Tc, eos_a=a, storage=storage)
+    p.pop("tau_nu", None)
+    p["s_nu"] = float(s_nu)
+    rl, rv = coexistence(T_over_Tc)
+    init = dict(droplets=[dict(center=(n / 2, n / 2, n / 2), r0=r0)], rho_L=rl, rho_V=rv, W=W)
+    return p, init
+
+
 def interface_recipe(T_over_Tc):
     """EOS constant a and initial interface width W for a reduced temperature:
     linear between the paper's T = 0.6 T_c setting (a = 0.25, W = 5, about

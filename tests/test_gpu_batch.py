@@ -170,3 +170,18 @@ def test_batch_diagnostics_and_status_per_run():
     assert bad["status"] == -4 and bad["nonfinite"] > 0
     assert "run 1" in binding.lbm_last_error()
     b.close()
+
+
+def test_batch_flags_the_diverging_run_only():
+    """Three FP64 runs, the middle one unstable (T = 0.5 T_c, s_nu = 1.9):
+    after 100 steps only that run reports non-finite populations."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    runs = [li.cold_droplet(1.0), li.cold_droplet(1.9), li.cold_droplet(1.0, n=20, T_over_Tc=0.6)]
+    print("[gpu] batch divergence runs s_nu=(1.0, 1.9, 1.0)", flush=True)
+    b = Batch([r[0] for r in runs])
+    for k, (p, init) in enumerate(runs):
+        b.init_fields(k, *li.init_fields(p, init))
+    b.step(100, 25)
+    assert b.status() == [0, -4, 0]
+    b.close()

@@ -599,3 +599,27 @@ def test_every_node_written_each_step(name, storage, mode, tile):
         lat.close()
     assert np.isfinite(out[1]).all()
     assert np.array_equal(out[0], out[1])
+
+
+def test_divergence_detected_on_device():
+    """The unstable low-viscosity droplet (T = 0.5 T_c, s_nu = 1.9) is flagged
+    non-finite by the device diagnostics; the stable one (s_nu = 1) stays
+    finite over 1000 steps and ends with the oracle's maximum velocity."""
+    _need_gpu()
+    cfg, init = li.cold_droplet(1.9)
+    print("[gpu] divergence s_nu=1.9 16^3 f64", flush=True)
+    lat = Lattice(cfg)
+    lat.init_fields(*li.init_fields(cfg, init)).step(100)
+    d = lat.diagnostics()
+    lat.close()
+    assert d["status"] == -4 and d["nonfinite"] > 0
+    cfg, init = li.cold_droplet(1.0)
+    rho, u = li.init_fields(cfg, init)
+    lat = Lattice(cfg)
+    lat.init_fields(rho, u).step(1000)
+    d = lat.diagnostics()
+    lat.close()
+    p = ref.make_params(cfg)
+    fl = ref.fields(p, ref.step(p, ref.equilibrium(p, rho, u), 1000))
+    want = float(np.sqrt((fl["u"] ** 2).sum(0)).max())
+    assert d["status"] == 0 and abs(d["max_u"] - want) <= 1e-8 * want

@@ -439,3 +439,27 @@ def test_closed_cavity_conserves_mass_and_z_mirror_symmetry(op):
     np.testing.assert_allclose(u[0], u[0][::-1], atol=1e-14)
     np.testing.assert_allclose(u[2], -u[2][::-1], atol=1e-14)
     assert u[0][:, -1, :].mean() > 0 > u[0][:, 0, :].mean()  # driven near the lid, return flow below
+
+
+def test_low_viscosity_diverges_within_bounded_steps():
+    """Failure detection on the CPU, at T = 0.5 T_c (density ratio about
+    724, where Sec. IV.A reports instability at small viscosity): s_nu = 1.9
+    (nu = 0.0088) blows up to non-finite populations within 100 steps, while
+    s_nu = 1 (nu = 1/6) stays finite over 1000 steps with its spurious
+    currents decaying below 0.01."""
+    for s_nu, steps in ((1.9, 100), (1.0, 1000)):
+        cfg, init = li.cold_droplet(s_nu)
+        p = ref.make_params(cfg)
+        f = ref.equilibrium(p, *li.init_fields(cfg, init))
+        first_bad = None
+        for k in range(0, steps, 10):
+            f = ref.step(p, f, 10)
+            if not np.isfinite(f).all():
+                first_bad = k + 10
+                break
+        if s_nu > 1.5:
+            assert first_bad is not None and first_bad <= 100
+        else:
+            assert first_bad is None
+            u = ref.fields(p, f)["u"]
+            assert float(np.sqrt((u ** 2).sum(0)).max()) < 0.01
