@@ -109,3 +109,17 @@ def test_make_params_mapping():
                                  storage="f16s", rho_ref=0.01, gravity=(0, 0, -1e-6), wall_z=1))
     assert (p.nx, p.ny, p.nz, p.wall_z, p.op, p.storage) == (8, 9, 10, 1, 1, 2)
     assert p.s_nu == 1.25 and p.s_eps == 1.4 and p.s_m == 1.2 and p.gravity[2] == -1e-6
+
+
+@pytest.mark.parametrize("storage,nz_max", [("f64", 262), ("f32", 524), ("f16s", 1048)])
+def test_largest_lattice_accepted_next_rejected(storage, nz_max):
+    """Five direction planes must fit the 32-bit buffer offsets (< 4 GiB):
+    640 x 640 x nz_max is the largest such lattice, one plane more is not."""
+    p = binding.lbm_params_default()
+    p.nx, p.ny, p.nz = 640, 640, nz_max
+    p.storage = binding.STORAGE[storage]
+    n = ctypes.c_size_t(0)
+    assert binding.lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == 0
+    p.nz = nz_max + 1
+    assert binding.lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == -5
+    assert "too large" in binding.lbm_last_error()

@@ -623,3 +623,99 @@ def test_divergence_detected_on_device():
     fl = ref.fields(p, ref.step(p, ref.equilibrium(p, rho, u), 1000))
     want = float(np.sqrt((fl["u"] ** 2).sum(0)).max())
     assert d["status"] == 0 and abs(d["max_u"] - want) <= 1e-8 * want
+
+
+# ---------------------------------------------------------------------------
+# Degenerate shapes: lattices one or two nodes thick along some axes.  With
+# n = 1 every stencil and streaming offset along that axis wraps onto the node
+# itself; with n = 2 both neighbours are the same node.  Walls need two planes.
+# ---------------------------------------------------------------------------
+DEGENERATE = [(1, 1, 24, 0), (24, 1, 1, 0), (1, 17, 1, 0), (6, 4, 1, 0), (5, 1, 9, 1), (2, 3, 2, 1),
+              (1, 1, 2, 1)]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("nx,ny,nz,wall", DEGENERATE)
+def test_degenerate_shapes_parity(nx, ny, nz, wall, storage):
+    cfg = li.params(nx, ny, nz, T_over_Tc=0.8, storage=storage, wall_z=wall,
+                    theta_wall_deg=70.0 if wall else 90.0)
+    rho, u = li.random_fields(nx, ny, nz, seed=100 * nx + 10 * ny + nz, rho_lo=0.05, rho_hi=0.3, umax=0.03)
+    cps = [1, 4]
+    got = gpu_states(cfg, rho, u, cps)
+    want = oracle_states(cfg, rho, u, cps)
+    for s, g, w in zip(cps, got, want):
+        e = rho_err(g, w)
+        bound = 1e-12 if storage == "f64" else 5e-6 * s
+        print(f"  step {s}: err {e:.3e} (bound {bound:.1e})")
+        assert e < bound, (s, e)
+
+
+def test_zero_steps_change_nothing():
+    """Stepping by zero is a no-op for a lattice and for a batch."""
+    _need_gpu()
+    cfg, rho, u, _ = _case("droplet_32", "nonorth", "f32")
+    lat = Lattice(cfg)
+    lat.init_fields(rho, u).step(2)
+    f0 = lat.read_populations().cpu().numpy()
+    n0 = lat.diagnostics()["step"]
+    lat.step(0)
+    assert lat.diagnostics()["step"] == n0 == 2
+    assert np.array_equal(lat.read_populations().cpu().numpy(), f0)
+    lat.close()
+    b = binding.Batch([cfg, cfg])
+    b.init_fields(0, rho, u)
+    b.init_fields(1, rho, u)
+    b.step(1, 0)
+    g0 = b.read_populations(1).cpu().numpy()
+    b.step(0, 4)
+    assert np.array_equal(b.read_populations(1).cpu().numpy(), g0)
+    assert b.diagnostics(1)["step"] == 1
+    b.close()
+
+
+# ---------------------------------------------------------------------------
+# Largest lattices the 32-bit buffer offsets allow (five direction planes
+# under 4 GiB), one per storage format.  The initial fields repeat with period
+# 64 x 64 x P, so the large lattice must reproduce, bit for bit, the small
+# periodic lattice at every sampled node; the small one is pinned to the
+# oracle.
+# ---------------------------------------------------------------------------
+MAX_SHAPES = {"f64": ((640, 640, 262), 2), "f32": ((640, 640, 524), 4), "f16s": ((640, 640, 1048), 4)}
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s"])
+def test_maximum_size_lattice(storage):
+    _need_gpu()
+    (nx, ny, nz), P = MAX_SHAPES[storage]
+    E = {"f64": 8, "f32": 4, "f16s": 2}[storage]
+    assert 5 * nx * ny * nz * E < 2 ** 32 <= 5 * nx * ny * (nz + 1) * E
+    small = li.params(64, 64, P, T_over_Tc=0.8, storage=storage)
+    if storage == "f16s":
+        small.update(rho_ref=li.coexistence(0.8)[1], f16_exp=f16_exp_for(1.25 * 0.3))
+    big = dict(small, nx=nx, ny=ny, nz=nz)
+    rho, u = li.random_fields(64, 64, P, seed=77, rho_lo=0.05, rho_hi=0.3, umax=0.03)
+    steps = 2
+    fs = gpu_states(small, rho, u, [steps])[0]
+    if storage == "f64":
+        want = oracle_states(small, rho, u, [steps])[0]
+        assert rho_err(fs, want) < 1e-12
+    reps = (nz // P, ny // 64, nx // 64)
+    rho_b = np.tile(rho.reshape(P, 64, 64), reps).reshape(-1)
+    u_b = np.tile(u.reshape(3, P, 64, 64), (1,) + reps).reshape(3, -1)
+    N = nx * ny * nz
+    rng = np.random.default_rng(7)
+    idx = np.unique(np.concatenate([rng.integers(0, N, 4000), [0, nx - 1, nx * ny - 1, N - nx * ny, N - 1]]))
+    print(f"[gpu] max size {nx}x{ny}x{nz} {storage} samples={idx.size}", flush=True)
+    lat = Lattice(big)
+    assert lat.N == N
+    lat.init_fields(rho_b, u_b)
+    del rho_b, u_b
+    lat.step(steps)
+    f = lat.read_populations()
+    got = f[:, torch.as_tensor(idx, device=f.device)].cpu().numpy()
+    del f
+    lat.close()
+    torch.cuda.empty_cache()
+    x, y, z = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    src = ((z % P) * 64 + y % 64) * 64 + x % 64
+    assert np.array_equal(got, fs[:, src])
