@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16s", "f64"])
     ap.add_argument("--op", default="nonorth", choices=["nonorth", "orth"])
-    ap.add_argument("--mode", default=None, choices=["fused", "pairs"],
+    ap.add_argument("--mode", default=None, choices=["fused", "pairs", "quads"],
                     help="step kernel; default: the faster one measured for the storage")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -191,11 +191,16 @@ def per_run_launches(cfgs, runs, steps):
     return N / (ms * 1e-3) / 1e6
 
 
+KERNEL_NAMES = {"fused": "k_step (fused psi/force + collide + pull-stream)",
+                "pairs": "k_step2 (fused psi/force + collide + pull-stream, two nodes per thread)",
+                "quads": "k_step4 (fused psi/force + collide + pull-stream, four nodes per thread)"}
+
+
 def read_traffic(storage, op, mode):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it covers this kernel built from the current sources; None otherwise."""
     from paper_1805_08643_amd.build import source_digest
-    kern = "step2" if mode == "pairs" else "step"
+    kern = {"pairs": "step2", "quads": "step4"}.get(mode, "step")
     path = os.path.join(ROOT, "profiles", f"{kern}_{WORKLOAD}_{storage}_{op}_pmc.md")
     if not os.path.exists(path):
         return None
@@ -336,15 +341,15 @@ def main():
                    "storage": a.storage, "op": a.op, "nodes": N, "tile": list(tile), "step_mode": mode},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                     "kernel": ("k_step2 (fused psi/force + collide + pull-stream, two nodes per thread)"
-                                if mode == "pairs" else "k_step (fused psi/force + collide + pull-stream)"),
+                     "kernel": KERNEL_NAMES.get(mode, KERNEL_NAMES["fused"]),
                      "kernel_ms": round(kms, 5), "algorithmic_bytes_per_node": bpn},
         "mass": diag["mass"], "nonfinite": diag["nonfinite"],
     }
     if not a.no_variants:
         var = {}
         for st, op, md in [("f32", "nonorth", "fused"), ("f32", "nonorth", "pairs"), ("f16s", "nonorth", "fused"),
-                           ("f16s", "nonorth", "pairs"), ("f32", "orth", None), ("f64", "nonorth", "fused")]:
+                           ("f16s", "nonorth", "pairs"), ("f16s", "nonorth", "quads"), ("f32", "orth", None),
+                           ("f64", "nonorth", "fused")]:
             key = f"{st}_{op}_{md or 'default'}"
             if (st, op) == (a.storage, a.op) and md in (None, mode):
                 var[key] = round(mlups, 1)

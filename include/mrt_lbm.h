@@ -210,20 +210,23 @@ lbm_status lbm_set_tile(lbm_ctx *ctx, const lbm_tile *t);
 lbm_status lbm_get_tile(const lbm_ctx *ctx, lbm_tile *t);
 lbm_status lbm_autotune(lbm_ctx *ctx, int32_t trials, lbm_tile *best);
 
-/* Step implementation.  LBM_STEP_FUSED (default): one kernel per step, tiles
- * marching in z with psi and its halo in LDS.  LBM_STEP_SLABS: per z-slab of
+/* Step implementation (all of one time step, Sec. II and Eq. (5)).
+ * LBM_STEP_FUSED: one kernel per step, tiles marching in z with psi and its
+ * halo in LDS, one node per thread.  LBM_STEP_SLABS: per z-slab of
  * slab_planes planes, a psi pass then a collide pass that re-reads the slab
  * (sized to stay in the last-level cache) and reads psi from a global array.
  * LBM_STEP_PAIRS: the fused kernel with two x-adjacent nodes per thread and
- * one wide access per direction for both; FP32 and F16S storage with even nx
- * only (else LBM_ERR_UNSUPPORTED), and the tile's tx must be even (set_tile
- * and this call return LBM_ERR_INVALID_ARG otherwise).  slab_planes is used
- * by LBM_STEP_SLABS only but must be >= 1.  All modes give the same
- * populations bit for bit.  A new context uses LBM_STEP_PAIRS with a
- * 128 x 8 (or narrower) tile where that mode applies and LBM_STEP_FUSED
- * otherwise.  Switching to LBM_STEP_PAIRS with an odd tile width replaces
- * the tile by that default. */
-enum { LBM_STEP_FUSED = 0, LBM_STEP_SLABS = 1, LBM_STEP_PAIRS = 2 };
+ * one wide access per direction for both; FP32 and F16S storage with even nx.
+ * LBM_STEP_QUADS: four x-adjacent nodes per thread, one 8-byte access per
+ * direction; F16S storage with nx a multiple of 4.  A mode that does not apply
+ * returns LBM_ERR_UNSUPPORTED.  With 2 or 4 nodes per thread the tile width
+ * must be a multiple of that count (lbm_set_tile returns LBM_ERR_INVALID_ARG
+ * otherwise); switching to such a mode with a tile that does not fit
+ * replaces the tile by the mode's default (rows of up to 128 nodes, up to 512
+ * threads).  slab_planes is used by LBM_STEP_SLABS only but must be >= 1.
+ * All modes give the same populations bit for bit.  A new context uses
+ * LBM_STEP_PAIRS where it applies and LBM_STEP_FUSED otherwise. */
+enum { LBM_STEP_FUSED = 0, LBM_STEP_SLABS = 1, LBM_STEP_PAIRS = 2, LBM_STEP_QUADS = 3 };
 lbm_status lbm_set_step_mode(lbm_ctx *ctx, int32_t mode, int32_t slab_planes);
 /* Current step mode and slab size (slab_planes may be NULL). */
 lbm_status lbm_get_step_mode(const lbm_ctx *ctx, int32_t *mode, int32_t *slab_planes);

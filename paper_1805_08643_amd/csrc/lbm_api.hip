@@ -174,21 +174,26 @@ Layout layout_of(const lbm_params &p) {
     return L;
 }
 
-// Threads of a step block: one per interior column (two columns per thread
-// in pair mode), and at least one per halo-ring node.
-int block_threads(int tx, int ty, bool pairs = false) {
+// Threads of a step block: one per npt interior columns (npt = 1, 2 or 4
+// x-adjacent nodes per thread), and at least one per halo-ring node.
+int block_threads(int tx, int ty, int npt = 1) {
     const int nh = 2 * (tx + 2) + 2 * ty;
-    const int n = std::max(pairs ? (tx / 2) * ty : tx * ty, nh);
+    const int n = std::max((tx / npt) * ty, nh);
     return (n + 63) / 64 * 64;
 }
 
+// Nodes per thread of a step mode.
+int npt_of(int mode) { return mode == LBM_STEP_QUADS ? 4 : (mode == LBM_STEP_PAIRS ? 2 : 1); }
+
 constexpr size_t kMaxStepLds = 65536;
 
-lbm_status check_tile(const lbm_tile &t, int storage, bool pairs = false) {
+lbm_status check_tile(const lbm_tile &t, int storage, int npt = 1) {
     if (t.tx < 1 || t.ty < 1 || t.cz < 1) return fail(LBM_ERR_INVALID_ARG, "tile dims must be positive");
     if (t.tx > 1024 || t.ty > 1024) return fail(LBM_ERR_INVALID_ARG, "tile dims must be <= 1024");
-    if (pairs && t.tx % 2) return fail(LBM_ERR_INVALID_ARG, "pair mode needs an even tile width, got %d", t.tx);
-    if ((pairs ? t.tx / 2 : t.tx) * t.ty > STEP_MAX_THREADS || block_threads(t.tx, t.ty, pairs) > STEP_MAX_THREADS)
+    if (t.tx % npt)
+        return fail(LBM_ERR_INVALID_ARG, "%d nodes per thread need a tile width that is a multiple of %d, got %d",
+                    npt, npt, t.tx);
+    if ((t.tx / npt) * t.ty > STEP_MAX_THREADS || block_threads(t.tx, t.ty, npt) > STEP_MAX_THREADS)
         return fail(LBM_ERR_INVALID_ARG, "tile %d x %d needs more than %d threads", t.tx, t.ty, STEP_MAX_THREADS);
     if (4 * (size_t)(t.ty + 2) * (t.tx + 2) * real_bytes(storage) > kMaxStepLds)
         return fail(LBM_ERR_INVALID_ARG, "tile %d x %d needs more than %zu bytes of LDS", t.tx, t.ty, kMaxStepLds);
@@ -235,15 +240,16 @@ lbm_tile default_tile(int nx, int ny, int nz) {
     return t;
 }
 
-// Default tile of pair mode: rows of up to 128 columns (64 thread pairs), up
-// to 512 interior threads, and z runs long enough that there are about as
-// many tiles as compute units (measured fastest at 256^3: 128 x 8 x 64).
-lbm_tile pair_tile(int nx, int ny, int nz) {
+// Default tile with npt = 2 or 4 nodes per thread: rows of up to 128
+// columns, up to 512 interior threads, and z runs long enough that there are
+// about as many tiles as compute units (measured fastest at 256^3: 128 x 8 x
+// 64 with pairs).
+lbm_tile wide_tile(int nx, int ny, int nz, int npt) {
     lbm_tile t{};
     t.tx = std::min(nx, 128);
-    t.tx += t.tx % 2;
-    t.ty = std::max(1, std::min(ny, STEP_MAX_THREADS / std::max(1, t.tx / 2)));
-    while (t.ty > 1 && block_threads(t.tx, t.ty, true) > STEP_MAX_THREADS) --t.ty;
+    t.tx = (t.tx + npt - 1) / npt * npt;
+    t.ty = std::max(1, std::min(ny, STEP_MAX_THREADS / std::max(1, t.tx / npt)));
+    while (t.ty > 1 && block_threads(t.tx, t.ty, npt) > STEP_MAX_THREADS) --t.ty;
     const int ncol = ((nx + t.tx - 1) / t.tx) * ((ny + t.ty - 1) / t.ty);
     const int nzc = std::max(1, (256 + ncol - 1) / ncol);
     t.cz = std::max(std::min(nz, 8), (nz + nzc - 1) / nzc);
@@ -252,6 +258,7 @@ lbm_tile pair_tile(int nx, int ny, int nz) {
 
 bool box_walls(const lbm_params &p) { return p.wall_x || p.wall_y; }
 bool pairs_apply(const lbm_params &p) { return p.storage != ST_F64 && p.nx % 2 == 0 && !box_walls(p); }
+bool quads_apply(const lbm_params &p) { return p.storage == ST_F16S && p.nx % 4 == 0 && !box_walls(p); }
 
 }  // namespace
 
@@ -332,7 +339,7 @@ size_t step_smem(const lbm_ctx *c, const GridDesc &g) {
     return 4 * (size_t)(g.ty + 2) * (g.tx + 2) * real_bytes(c->p.storage);
 }
 
-lbm_status launch_step(lbm_ctx *c, const GridDesc &g, const void *src, void *dst, bool pairs) {
+lbm_status launch_step(lbm_ctx *c, const GridDesc &g, const void *src, void *dst, int npt) {
     return dispatch(c, [&](auto S, auto O, auto W) -> lbm_status {
         using T = typename Storage<S.value>::T;
         using R = typename Storage<S.value>::R;
@@ -343,7 +350,20 @@ lbm_status launch_step(lbm_ctx *c, const GridDesc &g, const void *src, void *dst
             return LBM_OK;
         }
         const unsigned grid = 8u * (unsigned)g.per_xcd;
-        const int threads = block_threads(g.tx, g.ty, pairs);
+        const int threads = block_threads(g.tx, g.ty, npt);
+        if (npt == 4) {
+            if constexpr (S.value == ST_F16S) {
+                // nx and tx multiples of 4: checked by lbm_set_step_mode / lbm_set_tile
+                if (g.nx % 4 || g.tx % 4) return fail(LBM_ERR_INVALID_ARG, "quad mode needs nx and tile width % 4 == 0");
+                hipLaunchKernelGGL((k_step4<O.value, W.value>), dim3(grid), dim3(threads), step_smem(c, g), c->stream,
+                                   (const T *)src, (T *)dst, (const R *)c->gpsi(), g, c->pd);
+                HIP_TRY(hipGetLastError());
+                return LBM_OK;
+            } else {
+                return fail(LBM_ERR_UNSUPPORTED, "quad mode needs F16S storage");
+            }
+        }
+        const bool pairs = npt == 2;
         if constexpr (S.value != ST_F64) {
             if (pairs) {
                 // even nx and tx: checked by lbm_set_step_mode / lbm_set_tile
@@ -419,7 +439,7 @@ lbm_status one_step(lbm_ctx *c) {
     }
     if (c->mode == LBM_STEP_SLABS && !box_walls(c->p)) {
         if ((s = launch_slabs(c, c->state(), c->other()))) return s;
-    } else if ((s = launch_step(c, c->g, c->state(), c->other(), c->mode == LBM_STEP_PAIRS))) {
+    } else if ((s = launch_step(c, c->g, c->state(), c->other(), npt_of(c->mode)))) {
         return s;
     }
     if (c->timing) {
@@ -498,7 +518,7 @@ lbm_status lbm_create(const lbm_params *p, void *dev_ws, size_t ws_bytes, void *
     c->stream = static_cast<hipStream_t>(hip_stream);
     if (pairs_apply(*p)) {
         c->mode = LBM_STEP_PAIRS;
-        c->tile = pair_tile(p->nx, p->ny, p->nz);
+        c->tile = wide_tile(p->nx, p->ny, p->nz, 2);
     } else {
         c->tile = default_tile(p->nx, p->ny, p->nz);
     }
@@ -684,7 +704,7 @@ lbm_status lbm_load_state(lbm_ctx *c, const void *dev_buf, size_t bytes) {
 
 lbm_status lbm_set_tile(lbm_ctx *c, const lbm_tile *t) {
     if (!c || !t) return fail(LBM_ERR_INVALID_ARG, "null argument");
-    lbm_status s = check_tile(*t, c->p.storage, c->mode == LBM_STEP_PAIRS);
+    lbm_status s = check_tile(*t, c->p.storage, npt_of(c->mode));
     if (s) return s;
     c->tile = *t;
     c->tile.reserved = 0;
@@ -702,18 +722,18 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t trials, lbm_tile *best) {
     if (!c) return fail(LBM_ERR_INVALID_ARG, "ctx is NULL");
     if (trials < 1) return fail(LBM_ERR_INVALID_ARG, "trials < 1");
     std::vector<lbm_tile> cand;
-    const bool pairs = c->mode == LBM_STEP_PAIRS;
+    const int npt = npt_of(c->mode);
     const int txs[] = {16, 32, 64, 128, 256};
     const int tys[] = {1, 2, 4, 8, 16, 32};
     const int czs[] = {4, 8, 16, 32, 64, 128};
-    const int txmax = pairs ? 256 : 128;
+    const int txmax = npt > 1 ? 256 : 128;
     auto add = [&](int tx, int ty, int cz) {
         lbm_tile t{tx, ty, std::min(cz, c->p.nz), 0};
         if (tx > txmax) return;
         if (t.tx > c->p.nx && t.tx != std::min(c->p.nx, txmax)) return;
         if (t.ty > c->p.ny) return;
-        if ((pairs ? t.tx / 2 : t.tx) * t.ty < 64) return;
-        if (check_tile(t, c->p.storage, pairs) != LBM_OK) return;
+        if ((t.tx / npt) * t.ty < 64) return;
+        if (check_tile(t, c->p.storage, npt) != LBM_OK) return;
         for (auto &o : cand)
             if (o.tx == t.tx && o.ty == t.ty && o.cz == t.cz) return;
         cand.push_back(t);
@@ -721,7 +741,8 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t trials, lbm_tile *best) {
     for (int tx : txs)
         for (int ty : tys)
             for (int cz : czs) add(std::min(tx, c->p.nx), ty, cz);
-    if (cand.empty()) cand.push_back(pairs ? pair_tile(c->p.nx, c->p.ny, c->p.nz) : default_tile(c->p.nx, c->p.ny, c->p.nz));
+    if (cand.empty())
+        cand.push_back(npt > 1 ? wide_tile(c->p.nx, c->p.ny, c->p.nz, npt) : default_tile(c->p.nx, c->p.ny, c->p.nz));
     g_err.clear();
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
@@ -733,10 +754,10 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t trials, lbm_tile *best) {
     for (const lbm_tile &t : cand) {
         GridDesc g{};
         fill_grid(g, c->p, t);
-        if ((s = launch_step(c, g, c->state(), c->other(), pairs))) return s;  // warm-up
+        if ((s = launch_step(c, g, c->state(), c->other(), npt))) return s;  // warm-up
         HIP_TRY(hipEventRecord(e0, c->stream));
         for (int k = 0; k < trials; ++k)
-            if ((s = launch_step(c, g, c->state(), c->other(), pairs))) return s;
+            if ((s = launch_step(c, g, c->state(), c->other(), npt))) return s;
         HIP_TRY(hipEventRecord(e1, c->stream));
         HIP_TRY(hipEventSynchronize(e1));
         float ms = 0;
@@ -756,18 +777,21 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t trials, lbm_tile *best) {
 
 lbm_status lbm_set_step_mode(lbm_ctx *c, int32_t mode, int32_t slab_planes) {
     if (!c) return fail(LBM_ERR_INVALID_ARG, "ctx is NULL");
-    if (mode != LBM_STEP_FUSED && mode != LBM_STEP_SLABS && mode != LBM_STEP_PAIRS)
+    if (mode != LBM_STEP_FUSED && mode != LBM_STEP_SLABS && mode != LBM_STEP_PAIRS && mode != LBM_STEP_QUADS)
         return fail(LBM_ERR_INVALID_ARG, "unknown step mode %d", mode);
     if (slab_planes < 1) return fail(LBM_ERR_INVALID_ARG, "slab_planes < 1");
     if (mode == LBM_STEP_PAIRS) {
         if (c->p.storage == ST_F64) return fail(LBM_ERR_UNSUPPORTED, "pair mode needs FP32 or F16S storage");
         if (box_walls(c->p)) return fail(LBM_ERR_UNSUPPORTED, "runs with walls on x or y use their own kernel");
         if (c->p.nx % 2) return fail(LBM_ERR_UNSUPPORTED, "pair mode needs an even nx, got %d", c->p.nx);
-        if (check_tile(c->tile, c->p.storage, true) != LBM_OK) {
-            g_err.clear();
-            c->tile = pair_tile(c->p.nx, c->p.ny, c->p.nz);
-            fill_grid(c->g, c->p, c->tile);
-        }
+    }
+    if (mode == LBM_STEP_QUADS && !quads_apply(c->p))
+        return fail(LBM_ERR_UNSUPPORTED, "quad mode needs F16S storage, nx a multiple of 4 (got %d) and no walls on x or y",
+                    c->p.nx);
+    if (npt_of(mode) > 1 && check_tile(c->tile, c->p.storage, npt_of(mode)) != LBM_OK) {
+        g_err.clear();
+        c->tile = wide_tile(c->p.nx, c->p.ny, c->p.nz, npt_of(mode));
+        fill_grid(c->g, c->p, c->tile);
     }
     c->mode = mode;
     c->slab = slab_planes;
@@ -863,7 +887,7 @@ lbm_tile batch_tile(const lbm_params &p, int item_nodes, bool pairs) {
     else t.tx = default_tile(p.nx, p.ny, p.nz).tx;
     const int per_row = pairs ? t.tx / 2 : t.tx;
     t.ty = std::max(1, std::min(p.ny, STEP_MAX_THREADS / per_row));
-    while (t.ty > 1 && block_threads(t.tx, t.ty, pairs) > STEP_MAX_THREADS) --t.ty;
+    while (t.ty > 1 && block_threads(t.tx, t.ty, pairs ? 2 : 1) > STEP_MAX_THREADS) --t.ty;
     const int cols = t.tx * t.ty;
     t.cz = std::max(1, std::min(p.nz, (item_nodes + cols / 2) / cols));
     return t;
@@ -910,7 +934,7 @@ lbm_status batch_build(lbm_batch *b) {
         d.offB = b->run_off[k] + c->L.B;
         d.tile_begin = tiles;
         tiles += c->g.ntiles;
-        threads = std::max(threads, block_threads(c->g.tx, c->g.ty, b->pairs));
+        threads = std::max(threads, block_threads(c->g.tx, c->g.ty, b->pairs ? 2 : 1));
         smem = std::max(smem, step_smem(c, c->g));
         nodes += c->g.N;
     }

@@ -731,6 +731,326 @@ __global__ void LBM_STEP_ATTR
 }
 
 // ---------------------------------------------------------------------------
+// Four x-adjacent nodes per thread (F16S storage, nx a multiple of 4).
+//
+// One 8-byte access moves the four values of a direction.  Directions with
+// e_x = 0 read the aligned quad at xa; e_x = +1 reads the quad starting at
+// xa - 1 and e_x = -1 the one starting at xa + 1.  On the periodic seam (xa = 0
+// for e_x = +1, xa + 3 = nx - 1 for e_x = -1) the lane reads the aligned quad
+// and fetches the one wrapped value with a narrow load, as the pair kernel
+// does.  Populations stay in storage format in registers until a node is
+// converted for its psi and again for its collision; the results of the four
+// nodes are packed back into the halves of two registers per direction.  The
+// arithmetic per node is that of the one-node kernel: same populations bit
+// for bit.
+// ---------------------------------------------------------------------------
+struct Quad {
+    unsigned long long w[Q];  // four halves per direction
+};
+struct QuadSeam {
+    uint16_t sl[5], sr[5];  // wrapped seam values, left and right side
+};
+
+__device__ inline uint16_t q_half(unsigned long long w, int k) { return (uint16_t)(w >> (16 * k)); }
+
+// Byte offsets within one z-plane of one direction for a node quad.
+struct NbOff4 {
+    uint32_t c, ym, yp;    // aligned quad at xa, rows y, y-1, y+1
+    uint32_t xm, mm, pm;   // quad from xa - 1 (xa on the seam), rows y, y-1, y+1
+    uint32_t xp, mp, pp;   // quad from xa + 1 (xa + 3 on the seam), rows y, y-1, y+1
+    uint32_t ry, rym, ryp; // row starts, for the wrapped value on the seam
+    uint32_t xlast;        // (nx - 1) * 2
+    __device__ inline void set(int xa, bool wl, bool wr, int y, int ym_, int yp_, int nx) {
+        constexpr uint32_t E = 2;
+        const uint32_t rb = (uint32_t)nx * E;
+        ry = (uint32_t)y * rb;
+        rym = (uint32_t)ym_ * rb;
+        ryp = (uint32_t)yp_ * rb;
+        const uint32_t b0 = (uint32_t)xa * E;
+        const uint32_t bm = (uint32_t)(wl ? xa : xa - 1) * E;
+        const uint32_t bp = (uint32_t)(wr ? xa : xa + 1) * E;
+        c = ry + b0;
+        ym = rym + b0;
+        yp = ryp + b0;
+        xm = ry + bm;
+        mm = rym + bm;
+        pm = ryp + bm;
+        xp = ry + bp;
+        mp = rym + bp;
+        pp = ryp + bp;
+        xlast = (uint32_t)(nx - 1) * E;
+    }
+};
+
+__device__ inline uint32_t u_so(const PopBuf &A, int d, uint32_t plane) {
+    return __builtin_amdgcn_readfirstlane(A.so(d, plane));
+}
+
+// Issue the loads of a node quad at plane z (wl: xa == 0; wr: xa + 3 == nx - 1).
+template <bool WALL>
+__device__ inline void load4(const PopBuf &A, int nz, uint32_t PB, int z, const NbOff4 &o, Quad &r,
+                             QuadSeam &sm) {
+    const bool bot = WALL && z == 0;
+    const bool top = WALL && z == nz - 1;
+    const int zm = WALL ? (bot ? z : z - 1) : (z == 0 ? nz - 1 : z - 1);
+    const int zq = WALL ? (top ? z : z + 1) : (z == nz - 1 ? 0 : z + 1);
+    const uint32_t pc = __builtin_amdgcn_readfirstlane((uint32_t)z * PB);
+    const uint32_t pm = __builtin_amdgcn_readfirstlane((uint32_t)zm * PB);
+    const uint32_t pq = __builtin_amdgcn_readfirstlane((uint32_t)zq * PB);
+#define LBM_LQ(i, d, plane, off)                                                                               \
+    r.w[i] = __builtin_bit_cast(unsigned long long,                                                         \
+                                __builtin_amdgcn_raw_buffer_load_b64(A.of(d), (int)(off), (int)u_so(A, d, plane), \
+                                                                     LBM_BUF_AUX))
+    LBM_LQ(0, 0, pc, o.c);
+    LBM_LQ(1, 1, pc, o.xm);
+    LBM_LQ(2, 2, pc, o.xp);
+    LBM_LQ(3, 3, pc, o.ym);
+    LBM_LQ(4, 4, pc, o.yp);
+    LBM_LQ(7, 7, pc, o.mm);
+    LBM_LQ(8, 8, pc, o.pp);
+    LBM_LQ(9, 9, pc, o.pm);
+    LBM_LQ(10, 10, pc, o.mp);
+    if (!bot) {
+        LBM_LQ(5, 5, pm, o.c);
+        LBM_LQ(11, 11, pm, o.xm);
+        LBM_LQ(14, 14, pm, o.xp);
+        LBM_LQ(15, 15, pm, o.ym);
+        LBM_LQ(18, 18, pm, o.yp);
+    } else {
+        LBM_LQ(5, 6, pc, o.c);
+        LBM_LQ(11, 12, pc, o.c);
+        LBM_LQ(14, 13, pc, o.c);
+        LBM_LQ(15, 16, pc, o.c);
+        LBM_LQ(18, 17, pc, o.c);
+    }
+    if (!top) {
+        LBM_LQ(6, 6, pq, o.c);
+        LBM_LQ(12, 12, pq, o.xp);
+        LBM_LQ(13, 13, pq, o.xm);
+        LBM_LQ(16, 16, pq, o.yp);
+        LBM_LQ(17, 17, pq, o.ym);
+    } else {
+        LBM_LQ(6, 5, pc, o.c);
+        LBM_LQ(12, 11, pc, o.c);
+        LBM_LQ(13, 14, pc, o.c);
+        LBM_LQ(16, 15, pc, o.c);
+        LBM_LQ(17, 18, pc, o.c);
+    }
+#undef LBM_LQ
+#define LBM_L16(d, off, plane) \
+    (uint16_t) __builtin_amdgcn_raw_buffer_load_b16(A.of(d), (int)(off), (int)u_so(A, d, plane), LBM_BUF_AUX)
+    // Every lane issues the ten seam loads (from valid addresses; only seam
+    // lanes use the values), so each wave issues the same loads in the same
+    // order and the wait counts need no merging across branches.
+    const uint32_t pmb = bot ? pc : pm, pqt = top ? pc : pq;
+    sm.sl[0] = LBM_L16(1, o.ry + o.xlast, pc);  // order 1, 7, 9, 11, 13: value at x = nx - 1
+    sm.sl[1] = LBM_L16(7, o.rym + o.xlast, pc);
+    sm.sl[2] = LBM_L16(9, o.ryp + o.xlast, pc);
+    sm.sl[3] = LBM_L16(11, o.ry + o.xlast, pmb);
+    sm.sl[4] = LBM_L16(13, o.ry + o.xlast, pqt);
+    sm.sr[0] = LBM_L16(2, o.ry, pc);  // order 2, 8, 10, 14, 12: value at x = 0
+    sm.sr[1] = LBM_L16(8, o.ryp, pc);
+    sm.sr[2] = LBM_L16(10, o.rym, pc);
+    sm.sr[3] = LBM_L16(14, o.ry, pmb);
+    sm.sr[4] = LBM_L16(12, o.ry, pqt);
+#undef LBM_L16
+}
+
+// Once the loads of a plane have arrived, seam lanes shift the wrapped value
+// into the quads of the shifted directions: afterwards element k of every
+// quad is the value node k pulls.
+template <bool WALL>
+__device__ inline void fold_seams(Quad &r, const QuadSeam &sm, int nz, int z, bool wl, bool wr) {
+    const bool bot = WALL && z == 0;
+    const bool top = WALL && z == nz - 1;
+    auto left = [&](int i, int s) {  // e_x = +1: (seam, q0, q1, q2)
+        const unsigned long long v = (r.w[i] << 16) | (unsigned long long)sm.sl[s];
+        r.w[i] = wl ? v : r.w[i];
+    };
+    auto right = [&](int i, int s) {  // e_x = -1: (q1, q2, q3, seam)
+        const unsigned long long v = (r.w[i] >> 16) | ((unsigned long long)sm.sr[s] << 48);
+        r.w[i] = wr ? v : r.w[i];
+    };
+    left(1, 0);
+    left(7, 1);
+    left(9, 2);
+    if (!bot) left(11, 3);
+    if (!top) left(13, 4);
+    right(2, 0);
+    right(8, 1);
+    right(10, 2);
+    if (!bot) right(14, 3);
+    if (!top) right(12, 4);
+}
+
+// Populations of node k (0..3) of a folded quad, converted to FP32.
+__device__ inline void unpack4(const Quad &r, int k, const Phys<float> &P, float f[Q]) {
+#pragma unroll
+    for (int a = 0; a < Q; ++a) f[a] = fmaf(__half2float(__ushort_as_half(q_half(r.w[a], k))), P.hsi, P.sh(a));
+}
+
+// z-march of a tile with four nodes per thread: tx nodes (a multiple of 4)
+// by ty rows, (tx / 4) * ty interior threads; the halo ring is pulled one
+// node per thread as in tile_march.
+template <int OP, bool WALL>
+__device__ inline void tile_march4(const uint16_t *__restrict__ A, uint16_t *__restrict__ B,
+                                   const float *__restrict__ gpsi, const GridDesc &g, const Phys<float> &P,
+                                   int tile, float *ps) {
+    using R = float;
+    using H2 = _Float16 __attribute__((ext_vector_type(2)));
+    const int TX = g.tx, TY = g.ty, TXQ = g.tx >> 2;
+    const int SX = TX + 2, SP = (TY + 2) * SX;
+    int t = tile;
+    const int itx = t % g.ntx;
+    t /= g.ntx;
+    const int ity = t % g.nty;
+    const int izc = t / g.nty;
+    const int x0 = itx * TX, y0 = ity * TY;
+    const int zb = izc * g.cz;
+    const int ze = min(zb + g.cz, g.nz);
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const size_t N = (size_t)g.N;
+    const int tid = threadIdx.x;
+
+    // Interior quad of this thread: nodes x0 + 4 lx .. x0 + 4 lx + 3.  A quad
+    // starting at nx (a ragged last tile) supplies psi of the wrapped columns
+    // 0..3 to the last real column.
+    const int lx = tid % TXQ, ly = tid / TXQ;
+    const bool inner = ly < TY;
+    const int xa = x0 + 4 * lx;
+    const bool need_in = inner && xa <= nx && ly <= ny - y0;
+    const bool active = inner && xa < nx && y0 + ly < ny;
+    const int gx = xa >= nx ? xa - nx : xa, gy = wrapi(y0 + ly, ny);
+    const bool wl = gx == 0, wr = gx + 3 == nx - 1;
+    const int cin = (ly + 1) * SX + 4 * lx + 1;
+    constexpr uint32_t E = 2;
+    const uint32_t PB = (uint32_t)((size_t)nx * ny * E);
+    PopBuf bA, bB;
+    bA.set(A, N);
+    bB.set(B, N);
+    NbOff4 oin;
+    oin.set(gx, wl, wr, gy, wrapi(gy - 1, ny), wrapi(gy + 1, ny), nx);
+
+    const int nh = 2 * SX + 2 * TY;
+    int hlx = -1, hly = -1;
+    bool halo = false;
+    if (tid < nh) {
+        int h = tid;
+        if (h < SX) {
+            hlx = h - 1;
+            hly = -1;
+        } else if (h < 2 * SX) {
+            hlx = h - SX - 1;
+            hly = TY;
+        } else if (h < 2 * SX + TY) {
+            hlx = -1;
+            hly = h - 2 * SX;
+        } else {
+            hlx = TX;
+            hly = h - 2 * SX - TY;
+        }
+        halo = hlx <= nx - x0 && hly <= ny - y0;
+    }
+    const int hx = wrapi(x0 + hlx, nx), hy = wrapi(y0 + hly, ny);
+    const int chl = (hly + 1) * SX + hlx + 1;
+    NbOff oh;
+    oh.set(hx, wrapi(hx - 1, nx), wrapi(hx + 1, nx), hy, wrapi(hy - 1, ny), wrapi(hy + 1, ny), nx, E);
+
+    Quad cq, nq;  // planes z and z + 1, storage format
+    R rc[4] = {1, 1, 1, 1}, rn[4] = {1, 1, 1, 1};
+    auto zwrap = [&](int zp) { return WALL ? zp : wrapi(zp, nz); };
+    auto slot_of = [&](int z) { return ps + ((z - zb + 1) & 3) * SP; };
+    // Pull plane zp into q and put its psi in LDS; densities into rho.
+    auto pull_plane = [&](int zp, Quad &q, R *rho) {
+        R *slot = slot_of(zp);
+        if (WALL && (zp < 0 || zp >= nz)) {
+            const R *gp = gpsi + (zp < 0 ? 0 : (size_t)nx * ny);
+            if (need_in) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) slot[cin + k] = gp[(size_t)gy * nx + gx + k];
+            }
+            if (halo) slot[chl] = gp[(size_t)hy * nx + hx];
+            return;
+        }
+        const int zw = zwrap(zp);
+        // Interior loads, conversions and psi run on every lane (lanes
+        // without a pair of their own read valid nodes and keep the result
+        // to themselves), so the loads are consumed on the path that issued
+        // them; the halo node's loads likewise.
+        QuadSeam sm;
+        load4<WALL>(bA, nz, PB, zw, oin, q, sm);
+        if (halo) {
+            R fh[Q];
+            pull<ST_F16S, WALL>(bA, nz, PB, zw, oh, P, fh);
+            slot[chl] = pseudo_psi<R>(P, sum19<R>(fh));
+        }
+        fold_seams<WALL>(q, sm, nz, zw, wl, wr);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            R f[Q];
+            unpack4(q, k, P, f);
+            rho[k] = sum19<R>(f);
+            const R p = pseudo_psi<R>(P, rho[k]);
+            if (need_in) slot[cin + k] = p;
+        }
+    };
+
+    pull_plane(zb - 1, nq, rn);
+    pull_plane(zb, cq, rc);
+    for (int z = zb; z < ze; ++z) {
+        pull_plane(z + 1, nq, rn);
+        lds_barrier();
+        if (active) {
+            const R *lo = slot_of(z - 1), *mid = slot_of(z), *hi = slot_of(z + 1);
+            H2 plo[Q], phi[Q];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                R f[Q];
+                unpack4(cq, k, P, f);
+                R ax, ay, az;
+                psi_stencil<R>(lo, mid, hi, cin + k, SX, ax, ay, az);
+                const R rho = rc[k];
+                const R mG_psi = -P.G * mid[cin + k];
+                collide<R, OP>(f, rho, mG_psi * ax + rho * P.gx, mG_psi * ay + rho * P.gy, mG_psi * az + rho * P.gz,
+                               ax * ax + ay * ay + az * az, P);
+#pragma unroll
+                for (int a = 0; a < Q; ++a) {
+                    const _Float16 h = (_Float16)fmaf(f[a], P.hs, -P.shh(a));
+                    if (k == 0) plo[a].x = h;
+                    else if (k == 1) plo[a].y = h;
+                    else if (k == 2) phi[a].x = h;
+                    else phi[a].y = h;
+                }
+            }
+            const uint32_t pz = __builtin_amdgcn_readfirstlane((uint32_t)z * PB);
+#pragma unroll
+            for (int a = 0; a < Q; ++a) {
+                using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(bB.of(a), 0, 0, 0));
+                const unsigned long long w = (unsigned long long)__builtin_bit_cast(uint32_t, plo[a]) |
+                                             ((unsigned long long)__builtin_bit_cast(uint32_t, phi[a]) << 32);
+                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, w), bB.of(a), (int)oin.c,
+                                                      (int)u_so(bB, a, pz), LBM_BUF_STORE_AUX);
+            }
+        }
+        cq = nq;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) rc[k] = rn[k];
+    }
+}
+
+template <int OP, bool WALL>
+__global__ void LBM_STEP_ATTR k_step4(const uint16_t *__restrict__ A, uint16_t *__restrict__ B,
+                                      const float *__restrict__ gpsi, GridDesc g, PhysD pd) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float *ps = reinterpret_cast<float *>(smem_raw);
+    const int tile = xcd_tile(blockIdx.x, g.per_xcd);
+    if (tile >= g.ntiles) return;
+    Phys<float> P;
+    P.load(pd);
+    tile_march4<OP, WALL>(A, B, gpsi, g, P, tile, ps);
+}
+
+// ---------------------------------------------------------------------------
 // Single-phase step with walls on any axis (the lid-driven cavity of
 // Appendix B): no pseudopotential, one node per thread; the body force is
 // rho g.  Reads through box_source, writes at the node itself.

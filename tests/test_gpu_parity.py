@@ -105,6 +105,8 @@ CASES = {
     "droplet_32": lambda op: (*li.c1_droplet(op=op), (32, 8, 8)),
     "ragged_70x37x21": lambda op: (dict(li.c3_two_droplets(n=64, op=op)[0], nx=70, ny=37, nz=21),
                                    dict(li.c3_two_droplets(n=64)[1]), (32, 8, 8)),
+    "ragged_68x37x21": lambda op: (dict(li.c3_two_droplets(n=64, op=op)[0], nx=68, ny=37, nz=21),
+                                   dict(li.c3_two_droplets(n=64)[1]), (32, 8, 8)),
     "walls_40x33x19_60deg": lambda op: (*li.c4_sessile(60.0, nx=40, ny=33, nz=19, r0=8.0), (16, 8, 7)),
     "walls_37x20x12_120deg": lambda op: (*li.c4_sessile(120.0, nx=37, ny=20, nz=12, r0=6.0), (32, 4, 5)),
     # density-dependent viscosity: nu_L = 0.01 in the liquid, nu_V = 10 nu_L
@@ -168,9 +170,11 @@ def test_fp32_parity(name, op, mode):
         assert e < 5e-6 * s, (s, e)
 
 
-@pytest.mark.parametrize("mode", ["fused", "pairs"])
+@pytest.mark.parametrize("mode", ["fused", "pairs", "quads"])
 @pytest.mark.parametrize("name", ["droplet_32", "ragged_70x37x21", "walls_40x33x19_60deg"])
 def test_f16s_parity(name, mode):
+    if mode == "quads" and name == "ragged_70x37x21":
+        name = "ragged_68x37x21"  # quads need nx % 4 == 0
     cfg, rho, u, tile = _case(name, "nonorth", "f16s")
     cps = [1, 10]
     got = gpu_states(cfg, rho, u, cps, tile, mode)
@@ -300,6 +304,55 @@ def test_pair_mode_rejections():
     lat.set_step_mode("pairs")
     with pytest.raises(binding.LbmError) as e:
         lat.set_tile(15, 4, 4)
+    assert e.value.status == -1
+    lat.close()
+
+
+# Four nodes per thread (F16S): ragged tiles in x and y (with the wrap quad
+# that starts at nx), seam lanes at both ends, walls, a lattice one quad wide.
+QUAD_CASES = [("ragged_68x37x21", (32, 4, 7)), ("ragged_68x37x21", (68, 8, 21)), ("walls_40x33x19_60deg", (40, 4, 7)),
+              ("droplet_32", (32, 16, 8)), ("visc_two_droplets_48", (16, 8, 12))]
+
+
+@pytest.mark.parametrize("op", ["nonorth", "orth"])
+@pytest.mark.parametrize("name,tile", QUAD_CASES)
+def test_quad_mode_bit_identical_to_fused(name, tile, op):
+    cfg, rho, u, ftile = _case(name, op, "f16s")
+    fused = gpu_states(cfg, rho, u, [3], ftile, "fused")[0]
+    print(f"[gpu] quads {name} f16s {op} tile={tile}", flush=True)
+    lat = Lattice(cfg)
+    lat.set_step_mode("quads").set_tile(*tile)
+    lat.init_fields(rho, u).step(3)
+    got = lat.read_populations().cpu().numpy()
+    lat.close()
+    assert np.array_equal(got, fused)
+
+
+def test_quad_mode_one_quad_wide_lattice():
+    """nx = 4: one quad per row, on the seam at both ends at once."""
+    cfg = li.params(4, 6, 5, T_over_Tc=0.8, storage="f16s", rho_ref=0.02, f16_exp=f16_exp_for(0.4))
+    rho, u = li.random_fields(4, 6, 5, seed=12)
+    fused = gpu_states(cfg, rho, u, [2], (4, 6, 5), "fused")[0]
+    lat = Lattice(cfg)
+    lat.set_step_mode("quads").set_tile(4, 6, 5)
+    lat.init_fields(rho, u).step(2)
+    got = lat.read_populations().cpu().numpy()
+    lat.close()
+    assert np.array_equal(got, fused)
+
+
+def test_quad_mode_rejections():
+    _need_gpu()
+    for shape, storage in [((32, 8, 8), "f32"), ((32, 8, 8), "f64"), ((34, 8, 8), "f16s")]:
+        lat = Lattice(li.params(*shape, storage=storage))
+        with pytest.raises(binding.LbmError) as e:
+            lat.set_step_mode("quads")
+        assert e.value.status == -5, (shape, storage)
+        lat.close()
+    lat = Lattice(li.params(32, 8, 8, storage="f16s"))
+    lat.set_step_mode("quads")
+    with pytest.raises(binding.LbmError) as e:
+        lat.set_tile(30, 4, 4)
     assert e.value.status == -1
     lat.close()
 
@@ -570,7 +623,9 @@ def test_diagnostics_are_deterministic():
 WRITE_CHECK_CASES = [("ragged_70x37x21", "f32", "fused", None), ("ragged_70x37x21", "f16s", "pairs", (32, 4, 7)),
                      ("walls_40x33x19_60deg", "f64", "fused", None),
                      ("walls_40x33x19_60deg", "f32", "pairs", (16, 8, 7)),
-                     ("walls_37x20x12_120deg", "f32", "slabs", None), ("cavity", "f32", "fused", None)]
+                     ("walls_37x20x12_120deg", "f32", "slabs", None), ("cavity", "f32", "fused", None),
+                     ("ragged_68x37x21", "f16s", "quads", (32, 4, 7)),
+                     ("walls_40x33x19_60deg", "f16s", "quads", (40, 4, 7))]
 
 
 @pytest.mark.parametrize("name,storage,mode,tile", WRITE_CHECK_CASES)
@@ -587,8 +642,8 @@ def test_every_node_written_each_step(name, storage, mode, tile):
         lat = Lattice(cfg)
         if mode == "slabs":
             lat.set_step_mode("slabs", 5)
-        elif mode == "pairs":
-            lat.set_step_mode("pairs")
+        elif mode in ("pairs", "quads"):
+            lat.set_step_mode(mode)
         if tile is not None:
             lat.set_tile(*tile)
         lat.set_write_check(check)
