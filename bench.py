@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16s", "f64"])
     ap.add_argument("--op", default="nonorth", choices=["nonorth", "orth"])
-    ap.add_argument("--mode", default=None, choices=["fused", "pairs", "quads"],
+    ap.add_argument("--mode", default=None, choices=["fused", "pairs", "quads", "split"],
                     help="step kernel; default: the faster one measured for the storage")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -193,14 +193,16 @@ def per_run_launches(cfgs, runs, steps):
 
 KERNEL_NAMES = {"fused": "k_step (fused psi/force + collide + pull-stream)",
                 "pairs": "k_step2 (fused psi/force + collide + pull-stream, two nodes per thread)",
-                "quads": "k_step4 (fused psi/force + collide + pull-stream, four nodes per thread)"}
+                "quads": "k_step4 (fused psi/force + collide + pull-stream, four nodes per thread)",
+                "split": "k_step4s (psi/force + collide + pull-stream, four nodes per thread, pulling and colliding "
+                         "waves)"}
 
 
 def read_traffic(storage, op, mode):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it covers this kernel built from the current sources; None otherwise."""
     from paper_1805_08643_amd.build import source_digest
-    kern = {"pairs": "step2", "quads": "step4"}.get(mode, "step")
+    kern = {"pairs": "step2", "quads": "step4", "split": "step4s"}.get(mode, "step")
     path = os.path.join(ROOT, "profiles", f"{kern}_{WORKLOAD}_{storage}_{op}_pmc.md")
     if not os.path.exists(path):
         return None
@@ -348,7 +350,8 @@ def main():
     if not a.no_variants:
         var = {}
         for st, op, md in [("f32", "nonorth", "fused"), ("f32", "nonorth", "pairs"), ("f16s", "nonorth", "fused"),
-                           ("f16s", "nonorth", "pairs"), ("f16s", "nonorth", "quads"), ("f32", "orth", None),
+                           ("f16s", "nonorth", "pairs"), ("f16s", "nonorth", "quads"), ("f16s", "nonorth", "split"),
+                           ("f32", "orth", None),
                            ("f64", "nonorth", "fused")]:
             key = f"{st}_{op}_{md or 'default'}"
             if (st, op) == (a.storage, a.op) and md in (None, mode):

@@ -218,7 +218,12 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t trials, lbm_tile *best);
  * LBM_STEP_PAIRS: the fused kernel with two x-adjacent nodes per thread and
  * one wide access per direction for both; FP32 and F16S storage with even nx.
  * LBM_STEP_QUADS: four x-adjacent nodes per thread, one 8-byte access per
- * direction; F16S storage with nx a multiple of 4.  A mode that does not apply
+ * direction; F16S storage with nx a multiple of 4.  LBM_STEP_SPLIT: the same
+ * four-node arithmetic with the block split by wave into pullers (global
+ * loads, psi, populations into LDS) running three planes ahead of colliders
+ * (collision from LDS, stores), so memory and arithmetic overlap; F16S with
+ * nx a multiple of 4, tiles of at most 128 x 8 nodes (tx a multiple of 4).
+ * A mode that does not apply
  * returns LBM_ERR_UNSUPPORTED.  With 2 or 4 nodes per thread the tile width
  * must be a multiple of that count (lbm_set_tile returns LBM_ERR_INVALID_ARG
  * otherwise); switching to such a mode with a tile that does not fit
@@ -226,7 +231,7 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t trials, lbm_tile *best);
  * threads).  slab_planes is used by LBM_STEP_SLABS only but must be >= 1.
  * All modes give the same populations bit for bit.  A new context uses
  * LBM_STEP_PAIRS where it applies and LBM_STEP_FUSED otherwise. */
-enum { LBM_STEP_FUSED = 0, LBM_STEP_SLABS = 1, LBM_STEP_PAIRS = 2, LBM_STEP_QUADS = 3 };
+enum { LBM_STEP_FUSED = 0, LBM_STEP_SLABS = 1, LBM_STEP_PAIRS = 2, LBM_STEP_QUADS = 3, LBM_STEP_SPLIT = 4 };
 lbm_status lbm_set_step_mode(lbm_ctx *ctx, int32_t mode, int32_t slab_planes);
 /* Current step mode and slab size (slab_planes may be NULL). */
 lbm_status lbm_get_step_mode(const lbm_ctx *ctx, int32_t *mode, int32_t *slab_planes);

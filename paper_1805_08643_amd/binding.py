@@ -22,7 +22,7 @@ Q = 19
 OP = {"nonorth": 0, "orth": 1}
 STORAGE = {"f64": 0, "f32": 1, "f16s": 2}
 PSI = {"sqrt_cs": 0, "exp": 1}
-STEP_MODES = {"fused": 0, "slabs": 1, "pairs": 2, "quads": 3}
+STEP_MODES = {"fused": 0, "slabs": 1, "pairs": 2, "quads": 3, "split": 4}
 
 
 class LbmParams(ctypes.Structure):
@@ -451,7 +451,7 @@ class Lattice:
         return lbm_autotune(self.ctx, trials)
 
     def set_step_mode(self, mode, slab_planes=32):
-        """mode: "fused", "slabs", "pairs" or "quads"."""
+        """mode: "fused", "slabs", "pairs", "quads" or "split"."""
         lbm_set_step_mode(self.ctx, STEP_MODES[mode], slab_planes)
         return self
 

@@ -183,9 +183,23 @@ int block_threads(int tx, int ty, int npt = 1) {
 }
 
 // Nodes per thread of a step mode.
-int npt_of(int mode) { return mode == LBM_STEP_QUADS ? 4 : (mode == LBM_STEP_PAIRS ? 2 : 1); }
+int npt_of(int mode) {
+    return (mode == LBM_STEP_QUADS || mode == LBM_STEP_SPLIT) ? 4 : (mode == LBM_STEP_PAIRS ? 2 : 1);
+}
 
 constexpr size_t kMaxStepLds = 65536;
+
+// The split kernel's LDS holds tiles of up to SPLIT_TX x SPLIT_TY nodes,
+// SPLIT_ROLE quads per role.
+lbm_status check_split_tile(const lbm_tile &t) {
+    if (t.tx < 4 || t.ty < 1 || t.cz < 1 || t.tx % 4 || t.tx > SPLIT_TX || t.ty > SPLIT_TY ||
+        (t.tx / 4) * t.ty > SPLIT_ROLE)
+        return fail(LBM_ERR_INVALID_ARG, "split mode needs a tile width that is a multiple of 4 and at most %d, "
+                    "and at most %d rows; got %d x %d x %d", SPLIT_TX, SPLIT_TY, t.tx, t.ty, t.cz);
+    return LBM_OK;
+}
+
+lbm_tile split_tile(int nx, int ny, int nz);
 
 lbm_status check_tile(const lbm_tile &t, int storage, int npt = 1) {
     if (t.tx < 1 || t.ty < 1 || t.cz < 1) return fail(LBM_ERR_INVALID_ARG, "tile dims must be positive");
@@ -259,6 +273,18 @@ lbm_tile wide_tile(int nx, int ny, int nz, int npt) {
 bool box_walls(const lbm_params &p) { return p.wall_x || p.wall_y; }
 bool pairs_apply(const lbm_params &p) { return p.storage != ST_F64 && p.nx % 2 == 0 && !box_walls(p); }
 bool quads_apply(const lbm_params &p) { return p.storage == ST_F16S && p.nx % 4 == 0 && !box_walls(p); }
+
+// Default tile of the split mode: rows of up to 128 nodes, up to 8 rows, z
+// runs for about as many tiles as compute units.
+lbm_tile split_tile(int nx, int ny, int nz) {
+    lbm_tile t{};
+    t.tx = std::min(SPLIT_TX, (nx + 3) / 4 * 4);
+    t.ty = std::max(1, std::min(std::min(ny, SPLIT_TY), SPLIT_ROLE / (t.tx / 4)));
+    const int ncol = ((nx + t.tx - 1) / t.tx) * ((ny + t.ty - 1) / t.ty);
+    const int nzc = std::max(1, (256 + ncol - 1) / ncol);
+    t.cz = std::max(std::min(nz, 8), (nz + nzc - 1) / nzc);
+    return t;
+}
 
 }  // namespace
 
@@ -351,6 +377,19 @@ lbm_status launch_step(lbm_ctx *c, const GridDesc &g, const void *src, void *dst
         }
         const unsigned grid = 8u * (unsigned)g.per_xcd;
         const int threads = block_threads(g.tx, g.ty, npt);
+        if (c->mode == LBM_STEP_SPLIT) {
+            if constexpr (S.value == ST_F16S) {
+                lbm_tile t{g.tx, g.ty, g.cz, 0};
+                if (g.nx % 4) return fail(LBM_ERR_INVALID_ARG, "split mode needs nx a multiple of 4");
+                if (lbm_status e = check_split_tile(t)) return e;
+                hipLaunchKernelGGL((k_step4s<O.value, W.value>), dim3(grid), dim3(2 * SPLIT_ROLE), 0, c->stream,
+                                   (const T *)src, (T *)dst, (const R *)c->gpsi(), g, c->pd);
+                HIP_TRY(hipGetLastError());
+                return LBM_OK;
+            } else {
+                return fail(LBM_ERR_UNSUPPORTED, "split mode needs F16S storage");
+            }
+        }
         if (npt == 4) {
             if constexpr (S.value == ST_F16S) {
                 // nx and tx multiples of 4: checked by lbm_set_step_mode / lbm_set_tile
@@ -704,7 +743,7 @@ lbm_status lbm_load_state(lbm_ctx *c, const void *dev_buf, size_t bytes) {
 
 lbm_status lbm_set_tile(lbm_ctx *c, const lbm_tile *t) {
     if (!c || !t) return fail(LBM_ERR_INVALID_ARG, "null argument");
-    lbm_status s = check_tile(*t, c->p.storage, npt_of(c->mode));
+    lbm_status s = c->mode == LBM_STEP_SPLIT ? check_split_tile(*t) : check_tile(*t, c->p.storage, npt_of(c->mode));
     if (s) return s;
     c->tile = *t;
     c->tile.reserved = 0;
@@ -733,7 +772,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t trials, lbm_tile *best) {
         if (t.tx > c->p.nx && t.tx != std::min(c->p.nx, txmax)) return;
         if (t.ty > c->p.ny) return;
         if ((t.tx / npt) * t.ty < 64) return;
-        if (check_tile(t, c->p.storage, npt) != LBM_OK) return;
+        if ((c->mode == LBM_STEP_SPLIT ? check_split_tile(t) : check_tile(t, c->p.storage, npt)) != LBM_OK) return;
         for (auto &o : cand)
             if (o.tx == t.tx && o.ty == t.ty && o.cz == t.cz) return;
         cand.push_back(t);
@@ -742,7 +781,9 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t trials, lbm_tile *best) {
         for (int ty : tys)
             for (int cz : czs) add(std::min(tx, c->p.nx), ty, cz);
     if (cand.empty())
-        cand.push_back(npt > 1 ? wide_tile(c->p.nx, c->p.ny, c->p.nz, npt) : default_tile(c->p.nx, c->p.ny, c->p.nz));
+        cand.push_back(c->mode == LBM_STEP_SPLIT ? split_tile(c->p.nx, c->p.ny, c->p.nz)
+                       : npt > 1           ? wide_tile(c->p.nx, c->p.ny, c->p.nz, npt)
+                                           : default_tile(c->p.nx, c->p.ny, c->p.nz));
     g_err.clear();
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
@@ -777,7 +818,8 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t trials, lbm_tile *best) {
 
 lbm_status lbm_set_step_mode(lbm_ctx *c, int32_t mode, int32_t slab_planes) {
     if (!c) return fail(LBM_ERR_INVALID_ARG, "ctx is NULL");
-    if (mode != LBM_STEP_FUSED && mode != LBM_STEP_SLABS && mode != LBM_STEP_PAIRS && mode != LBM_STEP_QUADS)
+    if (mode != LBM_STEP_FUSED && mode != LBM_STEP_SLABS && mode != LBM_STEP_PAIRS && mode != LBM_STEP_QUADS &&
+        mode != LBM_STEP_SPLIT)
         return fail(LBM_ERR_INVALID_ARG, "unknown step mode %d", mode);
     if (slab_planes < 1) return fail(LBM_ERR_INVALID_ARG, "slab_planes < 1");
     if (mode == LBM_STEP_PAIRS) {
@@ -788,7 +830,16 @@ lbm_status lbm_set_step_mode(lbm_ctx *c, int32_t mode, int32_t slab_planes) {
     if (mode == LBM_STEP_QUADS && !quads_apply(c->p))
         return fail(LBM_ERR_UNSUPPORTED, "quad mode needs F16S storage, nx a multiple of 4 (got %d) and no walls on x or y",
                     c->p.nx);
-    if (npt_of(mode) > 1 && check_tile(c->tile, c->p.storage, npt_of(mode)) != LBM_OK) {
+    if (mode == LBM_STEP_SPLIT && !quads_apply(c->p))
+        return fail(LBM_ERR_UNSUPPORTED, "split mode needs F16S storage, nx a multiple of 4 (got %d) and no walls on x or y",
+                    c->p.nx);
+    if (mode == LBM_STEP_SPLIT) {
+        if (check_split_tile(c->tile) != LBM_OK) {
+            g_err.clear();
+            c->tile = split_tile(c->p.nx, c->p.ny, c->p.nz);
+            fill_grid(c->g, c->p, c->tile);
+        }
+    } else if (npt_of(mode) > 1 && check_tile(c->tile, c->p.storage, npt_of(mode)) != LBM_OK) {
         g_err.clear();
         c->tile = wide_tile(c->p.nx, c->p.ny, c->p.nz, npt_of(mode));
         fill_grid(c->g, c->p, c->tile);

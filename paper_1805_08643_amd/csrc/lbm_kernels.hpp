@@ -1051,6 +1051,204 @@ __global__ void LBM_STEP_ATTR k_step4(const uint16_t *__restrict__ A, uint16_t *
 }
 
 // ---------------------------------------------------------------------------
+// Producer/consumer split (F16S, four nodes per thread, tiles up to 128 x 8).
+//
+// A 512-thread block splits into two roles by wave: waves 0-3 pull planes
+// (global loads, psi into the LDS ring, populations in storage format and
+// densities into LDS), waves 4-7 collide planes from LDS and store them.  The
+// pullers run three planes ahead of the colliders, so on every SIMD one wave
+// waits on memory while the other computes: the two phases overlap instead
+// of alternating.  One barrier per plane; both roles run the same number of
+// iterations.  Per-node arithmetic is that of the one-node kernel, so the
+// populations are the same bit for bit.
+// ---------------------------------------------------------------------------
+constexpr int SPLIT_TX = 128, SPLIT_TY = 8, SPLIT_ROLE = 256;  // max tile, threads per role
+constexpr int SPLIT_SP = (SPLIT_TY + 2) * (SPLIT_TX + 2);     // psi ring slot
+
+template <int OP, bool WALL>
+__global__ void __launch_bounds__(2 * SPLIT_ROLE)
+    k_step4s(const uint16_t *__restrict__ A, uint16_t *__restrict__ B, const float *__restrict__ gpsi, GridDesc g,
+             PhysD pd) {
+    using R = float;
+    using H2 = _Float16 __attribute__((ext_vector_type(2)));
+    __shared__ unsigned long long qbuf[3][Q][SPLIT_ROLE];  // raw quads of three planes
+    __shared__ float rbuf[3][SPLIT_TX * SPLIT_TY];         // densities of three planes
+    __shared__ float ring[4][SPLIT_SP];                    // psi ring
+    const int tile = xcd_tile(blockIdx.x, g.per_xcd);
+    if (tile >= g.ntiles) return;
+    Phys<R> P;
+    P.load(pd);
+
+    const int TX = g.tx, TY = g.ty, TXQ = g.tx >> 2;
+    const int SX = TX + 2;
+    int t = tile;
+    const int itx = t % g.ntx;
+    t /= g.ntx;
+    const int ity = t % g.nty;
+    const int izc = t / g.nty;
+    const int x0 = itx * TX, y0 = ity * TY;
+    const int zb = izc * g.cz;
+    const int ze = min(zb + g.cz, g.nz);
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const size_t N = (size_t)g.N;
+    // Role by wave, read as wave-uniform so the roles are scalar branches.
+    const bool puller = __builtin_amdgcn_readfirstlane(threadIdx.x) < SPLIT_ROLE;
+    const int rid = puller ? threadIdx.x : threadIdx.x - SPLIT_ROLE;
+
+    // This thread's quad (either role): nodes x0 + 4 lx .. + 3 of row ly.
+    const int lx = rid % TXQ, ly = rid / TXQ;
+    const bool inner = ly < TY;
+    const int xa = x0 + 4 * lx;
+    const bool need_in = inner && xa <= nx && ly <= ny - y0;
+    const bool active = inner && xa < nx && y0 + ly < ny;
+    const int gx = xa >= nx ? xa - nx : xa, gy = wrapi(y0 + (inner ? ly : 0), ny);
+    const bool wl = gx == 0, wr = gx + 3 == nx - 1;
+    const int cin = (ly + 1) * SX + 4 * lx + 1;
+    const int qi = rid;  // quad slot in qbuf (ly * TXQ + lx)
+    const int nb = ly * TX + 4 * lx;  // first node slot in rbuf
+    constexpr uint32_t E = 2;
+    const uint32_t PB = (uint32_t)((size_t)nx * ny * E);
+    PopBuf bA, bB;
+    bA.set(A, N);
+    bB.set(B, N);
+    NbOff4 oin;
+    oin.set(gx, wl, wr, gy, wrapi(gy - 1, ny), wrapi(gy + 1, ny), nx);
+
+    // Halo ring: nh <= 2 * SPLIT_ROLE nodes, two per puller at most.
+    const int nh = 2 * SX + 2 * TY;
+    int chl[2];
+    bool halo[2];
+    NbOff oh[2];
+    int hxs[2], hys[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int h = rid + r * SPLIT_ROLE;
+        int hlx = -1, hly = -1;
+        halo[r] = false;
+        if (puller && h < nh) {
+            if (h < SX) {
+                hlx = h - 1;
+                hly = -1;
+            } else if (h < 2 * SX) {
+                hlx = h - SX - 1;
+                hly = TY;
+            } else if (h < 2 * SX + TY) {
+                hlx = -1;
+                hly = h - 2 * SX;
+            } else {
+                hlx = TX;
+                hly = h - 2 * SX - TY;
+            }
+            halo[r] = hlx <= nx - x0 && hly <= ny - y0;
+        }
+        hxs[r] = wrapi(x0 + hlx, nx);
+        hys[r] = wrapi(y0 + hly, ny);
+        chl[r] = (hly + 1) * SX + hlx + 1;
+        oh[r].set(hxs[r], wrapi(hxs[r] - 1, nx), wrapi(hxs[r] + 1, nx), hys[r], wrapi(hys[r] - 1, ny),
+                  wrapi(hys[r] + 1, ny), nx, E);
+    }
+    auto zwrap = [&](int zp) { return WALL ? zp : wrapi(zp, nz); };
+    auto rslot = [&](int z) { return ring[(z - zb + 1) & 3]; };
+    auto bslot = [&](int z) { return (z - zb + 3) % 3; };
+
+    // Puller: plane p into the LDS buffers.
+    auto pull_plane = [&](int p) {
+        R *slot = rslot(p);
+        if (WALL && (p < 0 || p >= nz)) {
+            const R *gp = gpsi + (p < 0 ? 0 : (size_t)nx * ny);
+            if (need_in) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) slot[cin + k] = gp[(size_t)gy * nx + gx + k];
+            }
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+                if (halo[r]) slot[chl[r]] = gp[(size_t)hys[r] * nx + hxs[r]];
+            return;
+        }
+        const int pw = zwrap(p);
+        Quad q;
+        QuadSeam sm;
+        load4<WALL>(bA, nz, PB, pw, oin, q, sm);
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            if (halo[r]) {
+                R fh[Q];
+                pull<ST_F16S, WALL>(bA, nz, PB, pw, oh[r], P, fh);
+                slot[chl[r]] = pseudo_psi<R>(P, sum19<R>(fh));
+            }
+        }
+        fold_seams<WALL>(q, sm, nz, pw, wl, wr);
+        const int bs = bslot(p);
+        if (active) {
+#pragma unroll
+            for (int a = 0; a < Q; ++a) qbuf[bs][a][qi] = q.w[a];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            R f[Q];
+            unpack4(q, k, P, f);
+            const R rho = sum19<R>(f);
+            const R psi = pseudo_psi<R>(P, rho);
+            if (need_in) slot[cin + k] = psi;
+            if (active) rbuf[bs][nb + k] = rho;
+        }
+    };
+    // Collider: plane c from the LDS buffers to B.
+    auto collide_plane = [&](int c) {
+        if (!active) return;
+        const int bs = bslot(c);
+        Quad q;
+#pragma unroll
+        for (int a = 0; a < Q; ++a) q.w[a] = qbuf[bs][a][qi];
+        const R *lo = rslot(c - 1), *mid = rslot(c), *hi = rslot(c + 1);
+        H2 plo[Q], phi[Q];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            R f[Q];
+            unpack4(q, k, P, f);
+            R ax, ay, az;
+            psi_stencil<R>(lo, mid, hi, cin + k, SX, ax, ay, az);
+            const R rho = rbuf[bs][nb + k];
+            const R mG_psi = -P.G * mid[cin + k];
+            collide<R, OP>(f, rho, mG_psi * ax + rho * P.gx, mG_psi * ay + rho * P.gy, mG_psi * az + rho * P.gz,
+                           ax * ax + ay * ay + az * az, P);
+#pragma unroll
+            for (int a = 0; a < Q; ++a) {
+                const _Float16 h = (_Float16)fmaf(f[a], P.hs, -P.shh(a));
+                if (k == 0) plo[a].x = h;
+                else if (k == 1) plo[a].y = h;
+                else if (k == 2) phi[a].x = h;
+                else phi[a].y = h;
+            }
+        }
+        const uint32_t pz = __builtin_amdgcn_readfirstlane((uint32_t)c * PB);
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(bB.of(a), 0, 0, 0));
+            const unsigned long long w = (unsigned long long)__builtin_bit_cast(uint32_t, plo[a]) |
+                                         ((unsigned long long)__builtin_bit_cast(uint32_t, phi[a]) << 32);
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, w), bB.of(a), (int)oin.c,
+                                                  (int)u_so(bB, a, pz), LBM_BUF_STORE_AUX);
+        }
+    };
+
+    // Iteration i: pullers take plane zb - 1 + i (up to ze), colliders plane
+    // zb - 3 + i (from zb to ze - 1).  Every thread runs every iteration and
+    // its barrier.
+    const int iters = (ze - zb) + 3;
+    for (int i = 0; i < iters; ++i) {
+        if (puller) {
+            const int p = zb - 1 + i;
+            if (p <= ze) pull_plane(p);
+        } else {
+            const int c = zb - 3 + i;
+            if (c >= zb) collide_plane(c);
+        }
+        lds_barrier();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Single-phase step with walls on any axis (the lid-driven cavity of
 // Appendix B): no pseudopotential, one node per thread; the body force is
 // rho g.  Reads through box_source, writes at the node itself.

@@ -4,8 +4,8 @@ either kernel give the same populations; these are the fastest found."""
 
 STEP_TILES = {
     # (workload, storage, mode) -> (tx, ty, cz); mode "fused": one node per
-    # thread, "pairs" / "quads": two / four x-adjacent nodes per thread (tx
-    # counts nodes)
+    # thread, "pairs" / "quads": two / four x-adjacent nodes per thread, "split":
+    # four per thread with pulling and colliding waves (tx counts nodes)
     ("droplet_32", "f64", "fused"): (32, 2, 4),
     ("laplace_128", "f64", "fused"): (128, 4, 16),
     ("laplace_128", "f32", "fused"): (64, 4, 16),
@@ -18,6 +18,7 @@ STEP_TILES = {
     ("two_droplets_256", "f16s", "fused"): (64, 4, 32),
     ("two_droplets_256", "f16s", "pairs"): (128, 8, 64),
     ("two_droplets_256", "f16s", "quads"): (128, 16, 32),
+    ("two_droplets_256", "f16s", "split"): (128, 8, 64),
     ("sessile_384x384x192", "f32", "fused"): (64, 4, 32),
     ("sessile_384x384x192", "f32", "pairs"): (128, 8, 16),
 }
@@ -26,7 +27,7 @@ STEP_TILES = {
 STEP_MODES = {
     ("laplace_128", "f16s"): "pairs",
     ("two_droplets_256", "f32"): "pairs",
-    ("two_droplets_256", "f16s"): "quads",
+    ("two_droplets_256", "f16s"): "split",
     ("sessile_384x384x192", "f32"): "pairs",
 }
 

@@ -170,10 +170,10 @@ def test_fp32_parity(name, op, mode):
         assert e < 5e-6 * s, (s, e)
 
 
-@pytest.mark.parametrize("mode", ["fused", "pairs", "quads"])
+@pytest.mark.parametrize("mode", ["fused", "pairs", "quads", "split"])
 @pytest.mark.parametrize("name", ["droplet_32", "ragged_70x37x21", "walls_40x33x19_60deg"])
 def test_f16s_parity(name, mode):
-    if mode == "quads" and name == "ragged_70x37x21":
+    if mode in ("quads", "split") and name == "ragged_70x37x21":
         name = "ragged_68x37x21"  # quads need nx % 4 == 0
     cfg, rho, u, tile = _case(name, "nonorth", "f16s")
     cps = [1, 10]
@@ -326,6 +326,43 @@ def test_quad_mode_bit_identical_to_fused(name, tile, op):
     got = lat.read_populations().cpu().numpy()
     lat.close()
     assert np.array_equal(got, fused)
+
+
+SPLIT_CASES = [("ragged_68x37x21", (32, 4, 7)), ("ragged_68x37x21", (68, 8, 21)), ("walls_40x33x19_60deg", (40, 4, 7)),
+               ("droplet_32", (32, 8, 8)), ("visc_two_droplets_48", (16, 8, 12))]
+
+
+@pytest.mark.parametrize("op", ["nonorth", "orth"])
+@pytest.mark.parametrize("name,tile", SPLIT_CASES)
+def test_split_mode_bit_identical_to_fused(name, tile, op):
+    """Pullers three planes ahead of colliders, planes handed over in LDS:
+    the same populations as the one-node kernel."""
+    cfg, rho, u, ftile = _case(name, op, "f16s")
+    fused = gpu_states(cfg, rho, u, [3], ftile, "fused")[0]
+    print(f"[gpu] split {name} f16s {op} tile={tile}", flush=True)
+    lat = Lattice(cfg)
+    lat.set_step_mode("split").set_tile(*tile)
+    lat.init_fields(rho, u).step(3)
+    got = lat.read_populations().cpu().numpy()
+    lat.close()
+    assert np.array_equal(got, fused)
+
+
+def test_split_mode_rejections():
+    _need_gpu()
+    for shape, storage in [((32, 8, 8), "f32"), ((34, 8, 8), "f16s")]:
+        lat = Lattice(li.params(*shape, storage=storage))
+        with pytest.raises(binding.LbmError) as e:
+            lat.set_step_mode("split")
+        assert e.value.status == -5, (shape, storage)
+        lat.close()
+    lat = Lattice(li.params(32, 32, 8, storage="f16s"))
+    lat.set_step_mode("split")
+    for tile in [(30, 4, 4), (32, 16, 4), (256, 1, 4)]:
+        with pytest.raises(binding.LbmError) as e:
+            lat.set_tile(*tile)
+        assert e.value.status == -1, tile
+    lat.close()
 
 
 def test_quad_mode_one_quad_wide_lattice():
@@ -625,7 +662,9 @@ WRITE_CHECK_CASES = [("ragged_70x37x21", "f32", "fused", None), ("ragged_70x37x2
                      ("walls_40x33x19_60deg", "f32", "pairs", (16, 8, 7)),
                      ("walls_37x20x12_120deg", "f32", "slabs", None), ("cavity", "f32", "fused", None),
                      ("ragged_68x37x21", "f16s", "quads", (32, 4, 7)),
-                     ("walls_40x33x19_60deg", "f16s", "quads", (40, 4, 7))]
+                     ("walls_40x33x19_60deg", "f16s", "quads", (40, 4, 7)),
+                     ("ragged_68x37x21", "f16s", "split", (32, 4, 7)),
+                     ("walls_40x33x19_60deg", "f16s", "split", (40, 4, 7))]
 
 
 @pytest.mark.parametrize("name,storage,mode,tile", WRITE_CHECK_CASES)
@@ -642,7 +681,7 @@ def test_every_node_written_each_step(name, storage, mode, tile):
         lat = Lattice(cfg)
         if mode == "slabs":
             lat.set_step_mode("slabs", 5)
-        elif mode in ("pairs", "quads"):
+        elif mode in ("pairs", "quads", "split"):
             lat.set_step_mode(mode)
         if tile is not None:
             lat.set_tile(*tile)
