@@ -194,15 +194,15 @@ def per_run_launches(cfgs, runs, steps):
 KERNEL_NAMES = {"fused": "k_step (fused psi/force + collide + pull-stream)",
                 "pairs": "k_step2 (fused psi/force + collide + pull-stream, two nodes per thread)",
                 "quads": "k_step4 (fused psi/force + collide + pull-stream, four nodes per thread)",
-                "split": "k_step4s (psi/force + collide + pull-stream, four nodes per thread, pulling and colliding "
-                         "waves)"}
+                "split": "k_step_split (psi/force + collide + pull-stream, 8-byte node groups, pulling and "
+                         "colliding waves)"}
 
 
 def read_traffic(storage, op, mode):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it covers this kernel built from the current sources; None otherwise."""
     from paper_1805_08643_amd.build import source_digest
-    kern = {"pairs": "step2", "quads": "step4", "split": "step4s"}.get(mode, "step")
+    kern = {"pairs": "step2", "quads": "step4", "split": "step_split"}.get(mode, "step")
     path = os.path.join(ROOT, "profiles", f"{kern}_{WORKLOAD}_{storage}_{op}_pmc.md")
     if not os.path.exists(path):
         return None
@@ -349,7 +349,8 @@ def main():
     }
     if not a.no_variants:
         var = {}
-        for st, op, md in [("f32", "nonorth", "fused"), ("f32", "nonorth", "pairs"), ("f16s", "nonorth", "fused"),
+        for st, op, md in [("f32", "nonorth", "fused"), ("f32", "nonorth", "pairs"), ("f32", "nonorth", "split"),
+                           ("f16s", "nonorth", "fused"),
                            ("f16s", "nonorth", "pairs"), ("f16s", "nonorth", "quads"), ("f16s", "nonorth", "split"),
                            ("f32", "orth", None),
                            ("f64", "nonorth", "fused")]:

@@ -218,11 +218,13 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t trials, lbm_tile *best);
  * LBM_STEP_PAIRS: the fused kernel with two x-adjacent nodes per thread and
  * one wide access per direction for both; FP32 and F16S storage with even nx.
  * LBM_STEP_QUADS: four x-adjacent nodes per thread, one 8-byte access per
- * direction; F16S storage with nx a multiple of 4.  LBM_STEP_SPLIT: the same
- * four-node arithmetic with the block split by wave into pullers (global
- * loads, psi, populations into LDS) running three planes ahead of colliders
- * (collision from LDS, stores), so memory and arithmetic overlap; F16S with
- * nx a multiple of 4, tiles of at most 128 x 8 nodes (tx a multiple of 4).
+ * direction; F16S storage with nx a multiple of 4.  LBM_STEP_SPLIT: 8-byte
+ * groups of nodes (four F16S or two FP32 per thread) with the block split by
+ * wave into pullers (global loads, psi, populations into LDS) running three
+ * planes ahead of colliders (collision from LDS, stores), so memory and
+ * arithmetic overlap; F16S with nx a multiple of 4 or FP32 with even nx; tile
+ * width a multiple of the group size and at most 128, at most 8 rows and 256
+ * groups (128 x 8 nodes for F16S, 128 x 4 for FP32).
  * A mode that does not apply
  * returns LBM_ERR_UNSUPPORTED.  With 2 or 4 nodes per thread the tile width
  * must be a multiple of that count (lbm_set_tile returns LBM_ERR_INVALID_ARG

@@ -182,24 +182,25 @@ int block_threads(int tx, int ty, int npt = 1) {
     return (n + 63) / 64 * 64;
 }
 
-// Nodes per thread of a step mode.
-int npt_of(int mode) {
-    return (mode == LBM_STEP_QUADS || mode == LBM_STEP_SPLIT) ? 4 : (mode == LBM_STEP_PAIRS ? 2 : 1);
+// Nodes per thread of a step mode (the split mode moves 8 bytes per access:
+// four F16S or two FP32 nodes).
+int npt_of(int mode, int storage) {
+    if (mode == LBM_STEP_SPLIT) return storage == ST_F16S ? 4 : 2;
+    return mode == LBM_STEP_QUADS ? 4 : (mode == LBM_STEP_PAIRS ? 2 : 1);
 }
 
 constexpr size_t kMaxStepLds = 65536;
 
 // The split kernel's LDS holds tiles of up to SPLIT_TX x SPLIT_TY nodes,
 // SPLIT_ROLE quads per role.
-lbm_status check_split_tile(const lbm_tile &t) {
-    if (t.tx < 4 || t.ty < 1 || t.cz < 1 || t.tx % 4 || t.tx > SPLIT_TX || t.ty > SPLIT_TY ||
-        (t.tx / 4) * t.ty > SPLIT_ROLE)
-        return fail(LBM_ERR_INVALID_ARG, "split mode needs a tile width that is a multiple of 4 and at most %d, "
-                    "and at most %d rows; got %d x %d x %d", SPLIT_TX, SPLIT_TY, t.tx, t.ty, t.cz);
+lbm_status check_split_tile(const lbm_tile &t, int npt) {
+    if (t.tx < npt || t.ty < 1 || t.cz < 1 || t.tx % npt || t.tx > SPLIT_TX || t.ty > SPLIT_TY ||
+        (t.tx / npt) * t.ty > SPLIT_ROLE || t.tx * t.ty > SPLIT_NODES)
+        return fail(LBM_ERR_INVALID_ARG, "split mode needs a tile width that is a multiple of %d and at most %d, at "
+                    "most %d rows and %d groups of %d nodes; got %d x %d x %d", npt, SPLIT_TX, SPLIT_TY,
+                    SPLIT_ROLE, npt, t.tx, t.ty, t.cz);
     return LBM_OK;
 }
-
-lbm_tile split_tile(int nx, int ny, int nz);
 
 lbm_status check_tile(const lbm_tile &t, int storage, int npt = 1) {
     if (t.tx < 1 || t.ty < 1 || t.cz < 1) return fail(LBM_ERR_INVALID_ARG, "tile dims must be positive");
@@ -273,13 +274,16 @@ lbm_tile wide_tile(int nx, int ny, int nz, int npt) {
 bool box_walls(const lbm_params &p) { return p.wall_x || p.wall_y; }
 bool pairs_apply(const lbm_params &p) { return p.storage != ST_F64 && p.nx % 2 == 0 && !box_walls(p); }
 bool quads_apply(const lbm_params &p) { return p.storage == ST_F16S && p.nx % 4 == 0 && !box_walls(p); }
+bool split_apply(const lbm_params &p) {
+    return !box_walls(p) && ((p.storage == ST_F16S && p.nx % 4 == 0) || (p.storage == ST_F32 && p.nx % 2 == 0));
+}
 
-// Default tile of the split mode: rows of up to 128 nodes, up to 8 rows, z
-// runs for about as many tiles as compute units.
-lbm_tile split_tile(int nx, int ny, int nz) {
+// Default tile of the split mode: rows of up to 128 nodes, up to
+// SPLIT_ROLE groups, z runs for about as many tiles as compute units.
+lbm_tile split_tile(int nx, int ny, int nz, int npt) {
     lbm_tile t{};
-    t.tx = std::min(SPLIT_TX, (nx + 3) / 4 * 4);
-    t.ty = std::max(1, std::min(std::min(ny, SPLIT_TY), SPLIT_ROLE / (t.tx / 4)));
+    t.tx = std::min(SPLIT_TX, (nx + npt - 1) / npt * npt);
+    t.ty = std::max(1, std::min(std::min(ny, SPLIT_TY), SPLIT_ROLE / (t.tx / npt)));
     const int ncol = ((nx + t.tx - 1) / t.tx) * ((ny + t.ty - 1) / t.ty);
     const int nzc = std::max(1, (256 + ncol - 1) / ncol);
     t.cz = std::max(std::min(nz, 8), (nz + nzc - 1) / nzc);
@@ -378,16 +382,16 @@ lbm_status launch_step(lbm_ctx *c, const GridDesc &g, const void *src, void *dst
         const unsigned grid = 8u * (unsigned)g.per_xcd;
         const int threads = block_threads(g.tx, g.ty, npt);
         if (c->mode == LBM_STEP_SPLIT) {
-            if constexpr (S.value == ST_F16S) {
+            if constexpr (S.value != ST_F64) {
                 lbm_tile t{g.tx, g.ty, g.cz, 0};
-                if (g.nx % 4) return fail(LBM_ERR_INVALID_ARG, "split mode needs nx a multiple of 4");
-                if (lbm_status e = check_split_tile(t)) return e;
-                hipLaunchKernelGGL((k_step4s<O.value, W.value>), dim3(grid), dim3(2 * SPLIT_ROLE), 0, c->stream,
-                                   (const T *)src, (T *)dst, (const R *)c->gpsi(), g, c->pd);
+                if (g.nx % npt) return fail(LBM_ERR_INVALID_ARG, "split mode needs nx a multiple of %d", npt);
+                if (lbm_status e = check_split_tile(t, npt)) return e;
+                hipLaunchKernelGGL((k_step_split<S.value, O.value, W.value>), dim3(grid), dim3(2 * SPLIT_ROLE), 0,
+                                   c->stream, (const T *)src, (T *)dst, (const R *)c->gpsi(), g, c->pd);
                 HIP_TRY(hipGetLastError());
                 return LBM_OK;
             } else {
-                return fail(LBM_ERR_UNSUPPORTED, "split mode needs F16S storage");
+                return fail(LBM_ERR_UNSUPPORTED, "split mode needs FP32 or F16S storage");
             }
         }
         if (npt == 4) {
@@ -478,7 +482,7 @@ lbm_status one_step(lbm_ctx *c) {
     }
     if (c->mode == LBM_STEP_SLABS && !box_walls(c->p)) {
         if ((s = launch_slabs(c, c->state(), c->other()))) return s;
-    } else if ((s = launch_step(c, c->g, c->state(), c->other(), npt_of(c->mode)))) {
+    } else if ((s = launch_step(c, c->g, c->state(), c->other(), npt_of(c->mode, c->p.storage)))) {
         return s;
     }
     if (c->timing) {
@@ -743,7 +747,8 @@ lbm_status lbm_load_state(lbm_ctx *c, const void *dev_buf, size_t bytes) {
 
 lbm_status lbm_set_tile(lbm_ctx *c, const lbm_tile *t) {
     if (!c || !t) return fail(LBM_ERR_INVALID_ARG, "null argument");
-    lbm_status s = c->mode == LBM_STEP_SPLIT ? check_split_tile(*t) : check_tile(*t, c->p.storage, npt_of(c->mode));
+    const int npt = npt_of(c->mode, c->p.storage);
+    lbm_status s = c->mode == LBM_STEP_SPLIT ? check_split_tile(*t, npt) : check_tile(*t, c->p.storage, npt);
     if (s) return s;
     c->tile = *t;
     c->tile.reserved = 0;
@@ -761,7 +766,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t trials, lbm_tile *best) {
     if (!c) return fail(LBM_ERR_INVALID_ARG, "ctx is NULL");
     if (trials < 1) return fail(LBM_ERR_INVALID_ARG, "trials < 1");
     std::vector<lbm_tile> cand;
-    const int npt = npt_of(c->mode);
+    const int npt = npt_of(c->mode, c->p.storage);
     const int txs[] = {16, 32, 64, 128, 256};
     const int tys[] = {1, 2, 4, 8, 16, 32};
     const int czs[] = {4, 8, 16, 32, 64, 128};
@@ -772,7 +777,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t trials, lbm_tile *best) {
         if (t.tx > c->p.nx && t.tx != std::min(c->p.nx, txmax)) return;
         if (t.ty > c->p.ny) return;
         if ((t.tx / npt) * t.ty < 64) return;
-        if ((c->mode == LBM_STEP_SPLIT ? check_split_tile(t) : check_tile(t, c->p.storage, npt)) != LBM_OK) return;
+        if ((c->mode == LBM_STEP_SPLIT ? check_split_tile(t, npt) : check_tile(t, c->p.storage, npt)) != LBM_OK) return;
         for (auto &o : cand)
             if (o.tx == t.tx && o.ty == t.ty && o.cz == t.cz) return;
         cand.push_back(t);
@@ -781,7 +786,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t trials, lbm_tile *best) {
         for (int ty : tys)
             for (int cz : czs) add(std::min(tx, c->p.nx), ty, cz);
     if (cand.empty())
-        cand.push_back(c->mode == LBM_STEP_SPLIT ? split_tile(c->p.nx, c->p.ny, c->p.nz)
+        cand.push_back(c->mode == LBM_STEP_SPLIT ? split_tile(c->p.nx, c->p.ny, c->p.nz, npt)
                        : npt > 1           ? wide_tile(c->p.nx, c->p.ny, c->p.nz, npt)
                                            : default_tile(c->p.nx, c->p.ny, c->p.nz));
     g_err.clear();
@@ -830,18 +835,19 @@ lbm_status lbm_set_step_mode(lbm_ctx *c, int32_t mode, int32_t slab_planes) {
     if (mode == LBM_STEP_QUADS && !quads_apply(c->p))
         return fail(LBM_ERR_UNSUPPORTED, "quad mode needs F16S storage, nx a multiple of 4 (got %d) and no walls on x or y",
                     c->p.nx);
-    if (mode == LBM_STEP_SPLIT && !quads_apply(c->p))
-        return fail(LBM_ERR_UNSUPPORTED, "split mode needs F16S storage, nx a multiple of 4 (got %d) and no walls on x or y",
-                    c->p.nx);
+    if (mode == LBM_STEP_SPLIT && !split_apply(c->p))
+        return fail(LBM_ERR_UNSUPPORTED, "split mode needs F16S storage with nx a multiple of 4 or FP32 with even nx "
+                    "(got nx = %d), and no walls on x or y", c->p.nx);
+    const int npt = npt_of(mode, c->p.storage);
     if (mode == LBM_STEP_SPLIT) {
-        if (check_split_tile(c->tile) != LBM_OK) {
+        if (check_split_tile(c->tile, npt) != LBM_OK) {
             g_err.clear();
-            c->tile = split_tile(c->p.nx, c->p.ny, c->p.nz);
+            c->tile = split_tile(c->p.nx, c->p.ny, c->p.nz, npt);
             fill_grid(c->g, c->p, c->tile);
         }
-    } else if (npt_of(mode) > 1 && check_tile(c->tile, c->p.storage, npt_of(mode)) != LBM_OK) {
+    } else if (npt > 1 && check_tile(c->tile, c->p.storage, npt) != LBM_OK) {
         g_err.clear();
-        c->tile = wide_tile(c->p.nx, c->p.ny, c->p.nz, npt_of(mode));
+        c->tile = wide_tile(c->p.nx, c->p.ny, c->p.nz, npt);
         fill_grid(c->g, c->p, c->tile);
     }
     c->mode = mode;

@@ -731,37 +731,86 @@ __global__ void LBM_STEP_ATTR
 }
 
 // ---------------------------------------------------------------------------
-// Four x-adjacent nodes per thread (F16S storage, nx a multiple of 4).
+// Eight-byte lanes: NPT x-adjacent nodes per thread in one 8-byte access per
+// direction (NPT = 4 for F16S storage, 2 for FP32).
 //
-// One 8-byte access moves the four values of a direction.  Directions with
-// e_x = 0 read the aligned quad at xa; e_x = +1 reads the quad starting at
-// xa - 1 and e_x = -1 the one starting at xa + 1.  On the periodic seam (xa = 0
-// for e_x = +1, xa + 3 = nx - 1 for e_x = -1) the lane reads the aligned quad
-// and fetches the one wrapped value with a narrow load, as the pair kernel
-// does.  Populations stay in storage format in registers until a node is
-// converted for its psi and again for its collision; the results of the four
-// nodes are packed back into the halves of two registers per direction.  The
-// arithmetic per node is that of the one-node kernel: same populations bit
-// for bit.
+// Directions with e_x = 0 read the aligned group at xa; e_x = +1 reads the
+// group starting at xa - 1 and e_x = -1 the one starting at xa + 1
+// (unaligned 8-byte loads, which gfx950 serves).  On the periodic seam (xa =
+// 0 for e_x = +1, xa + NPT - 1 = nx - 1 for e_x = -1) the lane reads the
+// aligned group and fetches the one wrapped value with a narrow load; once
+// the plane has arrived the wrapped value is shifted into the group, so that
+// element k of every group is the value node k pulls.  Populations stay in
+// storage format until a node is converted; the arithmetic per node is that
+// of the one-node kernel, so the populations are the same bit for bit.
 // ---------------------------------------------------------------------------
-struct Quad {
-    unsigned long long w[Q];  // four halves per direction
+template <int S> struct Lane8;
+template <> struct Lane8<ST_F16S> {
+    static constexpr int NPT = 4, BITS = 16;
+    using B = uint16_t;
+    __device__ static inline B narrow(rsrc_t r, uint32_t vo, uint32_t so) {
+        return (B)__builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, LBM_BUF_AUX);
+    }
+    __device__ static inline float cvt(unsigned long long w, int k, float shift, float hsi) {
+        return fmaf(__half2float(__ushort_as_half((uint16_t)(w >> (16 * k)))), hsi, shift);
+    }
 };
-struct QuadSeam {
-    uint16_t sl[5], sr[5];  // wrapped seam values, left and right side
+template <> struct Lane8<ST_F32> {
+    static constexpr int NPT = 2, BITS = 32;
+    using B = uint32_t;
+    __device__ static inline B narrow(rsrc_t r, uint32_t vo, uint32_t so) {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, LBM_BUF_AUX);
+    }
+    __device__ static inline float cvt(unsigned long long w, int k, float, float) {
+        return __uint_as_float((uint32_t)(w >> (32 * k)));
+    }
 };
 
-__device__ inline uint16_t q_half(unsigned long long w, int k) { return (uint16_t)(w >> (16 * k)); }
+struct Wide8 {
+    unsigned long long w[Q];  // NPT values per direction
+};
+template <int S> struct Seam8 {
+    typename Lane8<S>::B sl[5], sr[5];  // wrapped seam values, left and right side
+};
 
-// Byte offsets within one z-plane of one direction for a node quad.
-struct NbOff4 {
-    uint32_t c, ym, yp;    // aligned quad at xa, rows y, y-1, y+1
-    uint32_t xm, mm, pm;   // quad from xa - 1 (xa on the seam), rows y, y-1, y+1
-    uint32_t xp, mp, pp;   // quad from xa + 1 (xa + 3 on the seam), rows y, y-1, y+1
+// Results of the NPT nodes of a group, packed per direction for one 8-byte
+// store.  F16S converts straight into the halves of two registers.
+template <int S> struct Out8;
+template <> struct Out8<ST_F16S> {
+    using H2 = _Float16 __attribute__((ext_vector_type(2)));
+    H2 lo[Q], hi[Q];
+    __device__ inline void put(int k, int a, float v, const Phys<float> &P) {
+        const _Float16 h = (_Float16)fmaf(v, P.hs, -P.shh(a));
+        if (k == 0) lo[a].x = h;
+        else if (k == 1) lo[a].y = h;
+        else if (k == 2) hi[a].x = h;
+        else hi[a].y = h;
+    }
+    __device__ inline unsigned long long word(int a) const {
+        return (unsigned long long)__builtin_bit_cast(uint32_t, lo[a]) |
+               ((unsigned long long)__builtin_bit_cast(uint32_t, hi[a]) << 32);
+    }
+};
+template <> struct Out8<ST_F32> {
+    uint32_t lo[Q], hi[Q];
+    __device__ inline void put(int k, int a, float v, const Phys<float> &) {
+        if (k == 0) lo[a] = __float_as_uint(v);
+        else hi[a] = __float_as_uint(v);
+    }
+    __device__ inline unsigned long long word(int a) const {
+        return (unsigned long long)lo[a] | ((unsigned long long)hi[a] << 32);
+    }
+};
+
+// Byte offsets within one z-plane of one direction for a node group.
+template <int S> struct NbOff8 {
+    uint32_t c, ym, yp;    // aligned group at xa, rows y, y-1, y+1
+    uint32_t xm, mm, pm;   // group from xa - 1 (xa on the seam), rows y, y-1, y+1
+    uint32_t xp, mp, pp;   // group from xa + 1 (xa + NPT - 1 on the seam), rows y, y-1, y+1
     uint32_t ry, rym, ryp; // row starts, for the wrapped value on the seam
-    uint32_t xlast;        // (nx - 1) * 2
+    uint32_t xlast;        // (nx - 1) * sizeof(T)
     __device__ inline void set(int xa, bool wl, bool wr, int y, int ym_, int yp_, int nx) {
-        constexpr uint32_t E = 2;
+        constexpr uint32_t E = sizeof(typename Storage<S>::T);
         const uint32_t rb = (uint32_t)nx * E;
         ry = (uint32_t)y * rb;
         rym = (uint32_t)ym_ * rb;
@@ -786,10 +835,12 @@ __device__ inline uint32_t u_so(const PopBuf &A, int d, uint32_t plane) {
     return __builtin_amdgcn_readfirstlane(A.so(d, plane));
 }
 
-// Issue the loads of a node quad at plane z (wl: xa == 0; wr: xa + 3 == nx - 1).
-template <bool WALL>
-__device__ inline void load4(const PopBuf &A, int nz, uint32_t PB, int z, const NbOff4 &o, Quad &r,
-                             QuadSeam &sm) {
+// Issue the loads of a node group at plane z (wl: xa == 0; wr: xa + NPT - 1
+// == nx - 1).
+template <int S, bool WALL>
+__device__ inline void load8(const PopBuf &A, int nz, uint32_t PB, int z, const NbOff8<S> &o, Wide8 &r,
+                             Seam8<S> &sm) {
+    using L = Lane8<S>;
     const bool bot = WALL && z == 0;
     const bool top = WALL && z == nz - 1;
     const int zm = WALL ? (bot ? z : z - 1) : (z == 0 ? nz - 1 : z - 1);
@@ -837,38 +888,35 @@ __device__ inline void load4(const PopBuf &A, int nz, uint32_t PB, int z, const 
         LBM_LQ(17, 18, pc, o.c);
     }
 #undef LBM_LQ
-#define LBM_L16(d, off, plane) \
-    (uint16_t) __builtin_amdgcn_raw_buffer_load_b16(A.of(d), (int)(off), (int)u_so(A, d, plane), LBM_BUF_AUX)
     // Every lane issues the ten seam loads (from valid addresses; only seam
     // lanes use the values), so each wave issues the same loads in the same
     // order and the wait counts need no merging across branches.
     const uint32_t pmb = bot ? pc : pm, pqt = top ? pc : pq;
-    sm.sl[0] = LBM_L16(1, o.ry + o.xlast, pc);  // order 1, 7, 9, 11, 13: value at x = nx - 1
-    sm.sl[1] = LBM_L16(7, o.rym + o.xlast, pc);
-    sm.sl[2] = LBM_L16(9, o.ryp + o.xlast, pc);
-    sm.sl[3] = LBM_L16(11, o.ry + o.xlast, pmb);
-    sm.sl[4] = LBM_L16(13, o.ry + o.xlast, pqt);
-    sm.sr[0] = LBM_L16(2, o.ry, pc);  // order 2, 8, 10, 14, 12: value at x = 0
-    sm.sr[1] = LBM_L16(8, o.ryp, pc);
-    sm.sr[2] = LBM_L16(10, o.rym, pc);
-    sm.sr[3] = LBM_L16(14, o.ry, pmb);
-    sm.sr[4] = LBM_L16(12, o.ry, pqt);
-#undef LBM_L16
+    sm.sl[0] = L::narrow(A.of(1), o.ry + o.xlast, u_so(A, 1, pc));  // order 1, 7, 9, 11, 13: value at x = nx - 1
+    sm.sl[1] = L::narrow(A.of(7), o.rym + o.xlast, u_so(A, 7, pc));
+    sm.sl[2] = L::narrow(A.of(9), o.ryp + o.xlast, u_so(A, 9, pc));
+    sm.sl[3] = L::narrow(A.of(11), o.ry + o.xlast, u_so(A, 11, pmb));
+    sm.sl[4] = L::narrow(A.of(13), o.ry + o.xlast, u_so(A, 13, pqt));
+    sm.sr[0] = L::narrow(A.of(2), o.ry, u_so(A, 2, pc));  // order 2, 8, 10, 14, 12: value at x = 0
+    sm.sr[1] = L::narrow(A.of(8), o.ryp, u_so(A, 8, pc));
+    sm.sr[2] = L::narrow(A.of(10), o.rym, u_so(A, 10, pc));
+    sm.sr[3] = L::narrow(A.of(14), o.ry, u_so(A, 14, pmb));
+    sm.sr[4] = L::narrow(A.of(12), o.ry, u_so(A, 12, pqt));
 }
 
 // Once the loads of a plane have arrived, seam lanes shift the wrapped value
-// into the quads of the shifted directions: afterwards element k of every
-// quad is the value node k pulls.
-template <bool WALL>
-__device__ inline void fold_seams(Quad &r, const QuadSeam &sm, int nz, int z, bool wl, bool wr) {
+// into the groups of the shifted directions.
+template <int S, bool WALL>
+__device__ inline void fold8(Wide8 &r, const Seam8<S> &sm, int nz, int z, bool wl, bool wr) {
+    constexpr int BITS = Lane8<S>::BITS;
     const bool bot = WALL && z == 0;
     const bool top = WALL && z == nz - 1;
-    auto left = [&](int i, int s) {  // e_x = +1: (seam, q0, q1, q2)
-        const unsigned long long v = (r.w[i] << 16) | (unsigned long long)sm.sl[s];
+    auto left = [&](int i, int s) {  // e_x = +1: (seam, g0, .., g_{NPT-2})
+        const unsigned long long v = (r.w[i] << BITS) | (unsigned long long)sm.sl[s];
         r.w[i] = wl ? v : r.w[i];
     };
-    auto right = [&](int i, int s) {  // e_x = -1: (q1, q2, q3, seam)
-        const unsigned long long v = (r.w[i] >> 16) | ((unsigned long long)sm.sr[s] << 48);
+    auto right = [&](int i, int s) {  // e_x = -1: (g1, .., g_{NPT-1}, seam)
+        const unsigned long long v = (r.w[i] >> BITS) | ((unsigned long long)sm.sr[s] << (64 - BITS));
         r.w[i] = wr ? v : r.w[i];
     };
     left(1, 0);
@@ -883,10 +931,10 @@ __device__ inline void fold_seams(Quad &r, const QuadSeam &sm, int nz, int z, bo
     if (!top) right(12, 4);
 }
 
-// Populations of node k (0..3) of a folded quad, converted to FP32.
-__device__ inline void unpack4(const Quad &r, int k, const Phys<float> &P, float f[Q]) {
+// Populations of node k of a folded group, converted to FP32.
+template <int S> __device__ inline void unpack8(const Wide8 &r, int k, const Phys<float> &P, float f[Q]) {
 #pragma unroll
-    for (int a = 0; a < Q; ++a) f[a] = fmaf(__half2float(__ushort_as_half(q_half(r.w[a], k))), P.hsi, P.sh(a));
+    for (int a = 0; a < Q; ++a) f[a] = Lane8<S>::cvt(r.w[a], k, P.sh(a), P.hsi);
 }
 
 // z-march of a tile with four nodes per thread: tx nodes (a multiple of 4)
@@ -897,7 +945,6 @@ __device__ inline void tile_march4(const uint16_t *__restrict__ A, uint16_t *__r
                                    const float *__restrict__ gpsi, const GridDesc &g, const Phys<float> &P,
                                    int tile, float *ps) {
     using R = float;
-    using H2 = _Float16 __attribute__((ext_vector_type(2)));
     const int TX = g.tx, TY = g.ty, TXQ = g.tx >> 2;
     const int SX = TX + 2, SP = (TY + 2) * SX;
     int t = tile;
@@ -928,7 +975,7 @@ __device__ inline void tile_march4(const uint16_t *__restrict__ A, uint16_t *__r
     PopBuf bA, bB;
     bA.set(A, N);
     bB.set(B, N);
-    NbOff4 oin;
+    NbOff8<ST_F16S> oin;
     oin.set(gx, wl, wr, gy, wrapi(gy - 1, ny), wrapi(gy + 1, ny), nx);
 
     const int nh = 2 * SX + 2 * TY;
@@ -956,12 +1003,12 @@ __device__ inline void tile_march4(const uint16_t *__restrict__ A, uint16_t *__r
     NbOff oh;
     oh.set(hx, wrapi(hx - 1, nx), wrapi(hx + 1, nx), hy, wrapi(hy - 1, ny), wrapi(hy + 1, ny), nx, E);
 
-    Quad cq, nq;  // planes z and z + 1, storage format
+    Wide8 cq, nq;  // planes z and z + 1, storage format
     R rc[4] = {1, 1, 1, 1}, rn[4] = {1, 1, 1, 1};
     auto zwrap = [&](int zp) { return WALL ? zp : wrapi(zp, nz); };
     auto slot_of = [&](int z) { return ps + ((z - zb + 1) & 3) * SP; };
     // Pull plane zp into q and put its psi in LDS; densities into rho.
-    auto pull_plane = [&](int zp, Quad &q, R *rho) {
+    auto pull_plane = [&](int zp, Wide8 &q, R *rho) {
         R *slot = slot_of(zp);
         if (WALL && (zp < 0 || zp >= nz)) {
             const R *gp = gpsi + (zp < 0 ? 0 : (size_t)nx * ny);
@@ -977,18 +1024,18 @@ __device__ inline void tile_march4(const uint16_t *__restrict__ A, uint16_t *__r
         // without a pair of their own read valid nodes and keep the result
         // to themselves), so the loads are consumed on the path that issued
         // them; the halo node's loads likewise.
-        QuadSeam sm;
-        load4<WALL>(bA, nz, PB, zw, oin, q, sm);
+        Seam8<ST_F16S> sm;
+        load8<ST_F16S, WALL>(bA, nz, PB, zw, oin, q, sm);
         if (halo) {
             R fh[Q];
             pull<ST_F16S, WALL>(bA, nz, PB, zw, oh, P, fh);
             slot[chl] = pseudo_psi<R>(P, sum19<R>(fh));
         }
-        fold_seams<WALL>(q, sm, nz, zw, wl, wr);
+        fold8<ST_F16S, WALL>(q, sm, nz, zw, wl, wr);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             R f[Q];
-            unpack4(q, k, P, f);
+            unpack8<ST_F16S>(q, k, P, f);
             rho[k] = sum19<R>(f);
             const R p = pseudo_psi<R>(P, rho[k]);
             if (need_in) slot[cin + k] = p;
@@ -1002,11 +1049,11 @@ __device__ inline void tile_march4(const uint16_t *__restrict__ A, uint16_t *__r
         lds_barrier();
         if (active) {
             const R *lo = slot_of(z - 1), *mid = slot_of(z), *hi = slot_of(z + 1);
-            H2 plo[Q], phi[Q];
+            Out8<ST_F16S> out;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 R f[Q];
-                unpack4(cq, k, P, f);
+                unpack8<ST_F16S>(cq, k, P, f);
                 R ax, ay, az;
                 psi_stencil<R>(lo, mid, hi, cin + k, SX, ax, ay, az);
                 const R rho = rc[k];
@@ -1014,21 +1061,13 @@ __device__ inline void tile_march4(const uint16_t *__restrict__ A, uint16_t *__r
                 collide<R, OP>(f, rho, mG_psi * ax + rho * P.gx, mG_psi * ay + rho * P.gy, mG_psi * az + rho * P.gz,
                                ax * ax + ay * ay + az * az, P);
 #pragma unroll
-                for (int a = 0; a < Q; ++a) {
-                    const _Float16 h = (_Float16)fmaf(f[a], P.hs, -P.shh(a));
-                    if (k == 0) plo[a].x = h;
-                    else if (k == 1) plo[a].y = h;
-                    else if (k == 2) phi[a].x = h;
-                    else phi[a].y = h;
-                }
+                for (int a = 0; a < Q; ++a) out.put(k, a, f[a], P);
             }
             const uint32_t pz = __builtin_amdgcn_readfirstlane((uint32_t)z * PB);
 #pragma unroll
             for (int a = 0; a < Q; ++a) {
                 using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(bB.of(a), 0, 0, 0));
-                const unsigned long long w = (unsigned long long)__builtin_bit_cast(uint32_t, plo[a]) |
-                                             ((unsigned long long)__builtin_bit_cast(uint32_t, phi[a]) << 32);
-                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, w), bB.of(a), (int)oin.c,
+                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, out.word(a)), bB.of(a), (int)oin.c,
                                                       (int)u_so(bB, a, pz), LBM_BUF_STORE_AUX);
             }
         }
@@ -1051,35 +1090,39 @@ __global__ void LBM_STEP_ATTR k_step4(const uint16_t *__restrict__ A, uint16_t *
 }
 
 // ---------------------------------------------------------------------------
-// Producer/consumer split (F16S, four nodes per thread, tiles up to 128 x 8).
+// Split step: pulling and colliding waves (FP32 and F16S, eight-byte lanes).
 //
-// A 512-thread block splits into two roles by wave: waves 0-3 pull planes
-// (global loads, psi into the LDS ring, populations in storage format and
-// densities into LDS), waves 4-7 collide planes from LDS and store them.  The
-// pullers run three planes ahead of the colliders, so on every SIMD one wave
-// waits on memory while the other computes: the two phases overlap instead
-// of alternating.  One barrier per plane; both roles run the same number of
-// iterations.  Per-node arithmetic is that of the one-node kernel, so the
-// populations are the same bit for bit.
+// A 512-thread block splits into two roles by wave.  Waves 0-3 pull planes:
+// global loads, psi into the LDS ring, populations (storage format) and
+// densities into LDS.  Waves 4-7 collide planes from LDS and store them.  The pullers
+// run three planes ahead of the colliders, so on every SIMD one wave waits on
+// memory while the other computes and the two phases overlap instead of
+// alternating.  One barrier per plane; both roles run the same
+// number of iterations.  Tiles hold at most SPLIT_ROLE groups of NPT nodes
+// (128 x 8 nodes for F16S, 128 x 4 for FP32), so that three planes of
+// populations fit in LDS.  Per-node arithmetic is that of the one-node
+// kernel: the same populations bit for bit.
 // ---------------------------------------------------------------------------
-constexpr int SPLIT_TX = 128, SPLIT_TY = 8, SPLIT_ROLE = 256;  // max tile, threads per role
+constexpr int SPLIT_TX = 128, SPLIT_TY = 8, SPLIT_ROLE = 256;  // max tile width / rows, threads per role
 constexpr int SPLIT_SP = (SPLIT_TY + 2) * (SPLIT_TX + 2);     // psi ring slot
+constexpr int SPLIT_NODES = 1024;                               // max nodes per tile plane
 
-template <int OP, bool WALL>
+template <int S, int OP, bool WALL>
 __global__ void __launch_bounds__(2 * SPLIT_ROLE)
-    k_step4s(const uint16_t *__restrict__ A, uint16_t *__restrict__ B, const float *__restrict__ gpsi, GridDesc g,
-             PhysD pd) {
+    k_step_split(const typename Storage<S>::T *__restrict__ A, typename Storage<S>::T *__restrict__ B,
+                 const float *__restrict__ gpsi, GridDesc g, PhysD pd) {
     using R = float;
-    using H2 = _Float16 __attribute__((ext_vector_type(2)));
-    __shared__ unsigned long long qbuf[3][Q][SPLIT_ROLE];  // raw quads of three planes
-    __shared__ float rbuf[3][SPLIT_TX * SPLIT_TY];         // densities of three planes
+    using T = typename Storage<S>::T;
+    constexpr int NPT = Lane8<S>::NPT;
+    __shared__ unsigned long long qbuf[3][Q][SPLIT_ROLE];  // populations of three planes, one group per slot
+    __shared__ float rbuf[3][SPLIT_NODES];                 // densities of three planes
     __shared__ float ring[4][SPLIT_SP];                    // psi ring
     const int tile = xcd_tile(blockIdx.x, g.per_xcd);
     if (tile >= g.ntiles) return;
     Phys<R> P;
     P.load(pd);
 
-    const int TX = g.tx, TY = g.ty, TXQ = g.tx >> 2;
+    const int TX = g.tx, TY = g.ty, TXG = g.tx / NPT;
     const int SX = TX + 2;
     int t = tile;
     const int itx = t % g.ntx;
@@ -1095,31 +1138,31 @@ __global__ void __launch_bounds__(2 * SPLIT_ROLE)
     const bool puller = __builtin_amdgcn_readfirstlane(threadIdx.x) < SPLIT_ROLE;
     const int rid = puller ? threadIdx.x : threadIdx.x - SPLIT_ROLE;
 
-    // This thread's quad (either role): nodes x0 + 4 lx .. + 3 of row ly.
-    const int lx = rid % TXQ, ly = rid / TXQ;
+    // This thread's group (either role): nodes x0 + NPT lx .. + NPT - 1 of row
+    // ly.  A group starting at nx (a ragged last tile) supplies psi of the
+    // wrapped columns to the last real column.
+    const int lx = rid % TXG, ly = rid / TXG;
     const bool inner = ly < TY;
-    const int xa = x0 + 4 * lx;
+    const int xa = x0 + NPT * lx;
     const bool need_in = inner && xa <= nx && ly <= ny - y0;
     const bool active = inner && xa < nx && y0 + ly < ny;
     const int gx = xa >= nx ? xa - nx : xa, gy = wrapi(y0 + (inner ? ly : 0), ny);
-    const bool wl = gx == 0, wr = gx + 3 == nx - 1;
-    const int cin = (ly + 1) * SX + 4 * lx + 1;
-    const int qi = rid;  // quad slot in qbuf (ly * TXQ + lx)
-    const int nb = ly * TX + 4 * lx;  // first node slot in rbuf
-    constexpr uint32_t E = 2;
+    const bool wl = gx == 0, wr = gx + NPT - 1 == nx - 1;
+    const int cin = (ly + 1) * SX + NPT * lx + 1;
+    const int nb = ly * TX + NPT * lx;  // first node slot in rbuf
+    constexpr uint32_t E = sizeof(T);
     const uint32_t PB = (uint32_t)((size_t)nx * ny * E);
     PopBuf bA, bB;
     bA.set(A, N);
     bB.set(B, N);
-    NbOff4 oin;
+    NbOff8<S> oin;
     oin.set(gx, wl, wr, gy, wrapi(gy - 1, ny), wrapi(gy + 1, ny), nx);
 
-    // Halo ring: nh <= 2 * SPLIT_ROLE nodes, two per puller at most.
+    // Halo ring: nh <= 2 * SPLIT_ROLE nodes, at most two per puller.
     const int nh = 2 * SX + 2 * TY;
-    int chl[2];
+    int chl[2], hxs[2], hys[2];
     bool halo[2];
     NbOff oh[2];
-    int hxs[2], hys[2];
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
         const int h = rid + r * SPLIT_ROLE;
@@ -1151,14 +1194,16 @@ __global__ void __launch_bounds__(2 * SPLIT_ROLE)
     auto rslot = [&](int z) { return ring[(z - zb + 1) & 3]; };
     auto bslot = [&](int z) { return (z - zb + 3) % 3; };
 
-    // Puller: plane p into the LDS buffers.
+    // Puller: plane p into the LDS buffers.  (Issuing the next plane's loads
+    // before the barrier, to keep them in flight while it waits, measured
+    // slower.)
     auto pull_plane = [&](int p) {
         R *slot = rslot(p);
         if (WALL && (p < 0 || p >= nz)) {
             const R *gp = gpsi + (p < 0 ? 0 : (size_t)nx * ny);
             if (need_in) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) slot[cin + k] = gp[(size_t)gy * nx + gx + k];
+                for (int k = 0; k < NPT; ++k) slot[cin + k] = gp[(size_t)gy * nx + gx + k];
             }
 #pragma unroll
             for (int r = 0; r < 2; ++r)
@@ -1166,27 +1211,28 @@ __global__ void __launch_bounds__(2 * SPLIT_ROLE)
             return;
         }
         const int pw = zwrap(p);
-        Quad q;
-        QuadSeam sm;
-        load4<WALL>(bA, nz, PB, pw, oin, q, sm);
+        Wide8 q;
+        Seam8<S> sm;
+        load8<S, WALL>(bA, nz, PB, pw, oin, q, sm);
+        // The halo node's loads are consumed in the branch that issued them.
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
             if (halo[r]) {
                 R fh[Q];
-                pull<ST_F16S, WALL>(bA, nz, PB, pw, oh[r], P, fh);
+                pull<S, WALL>(bA, nz, PB, pw, oh[r], P, fh);
                 slot[chl[r]] = pseudo_psi<R>(P, sum19<R>(fh));
             }
         }
-        fold_seams<WALL>(q, sm, nz, pw, wl, wr);
+        fold8<S, WALL>(q, sm, nz, pw, wl, wr);
         const int bs = bslot(p);
         if (active) {
 #pragma unroll
-            for (int a = 0; a < Q; ++a) qbuf[bs][a][qi] = q.w[a];
+            for (int a = 0; a < Q; ++a) qbuf[bs][a][rid] = q.w[a];
         }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < NPT; ++k) {
             R f[Q];
-            unpack4(q, k, P, f);
+            unpack8<S>(q, k, P, f);
             const R rho = sum19<R>(f);
             const R psi = pseudo_psi<R>(P, rho);
             if (need_in) slot[cin + k] = psi;
@@ -1197,15 +1243,15 @@ __global__ void __launch_bounds__(2 * SPLIT_ROLE)
     auto collide_plane = [&](int c) {
         if (!active) return;
         const int bs = bslot(c);
-        Quad q;
+        Wide8 q;
 #pragma unroll
-        for (int a = 0; a < Q; ++a) q.w[a] = qbuf[bs][a][qi];
+        for (int a = 0; a < Q; ++a) q.w[a] = qbuf[bs][a][rid];
         const R *lo = rslot(c - 1), *mid = rslot(c), *hi = rslot(c + 1);
-        H2 plo[Q], phi[Q];
+        Out8<S> out;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < NPT; ++k) {
             R f[Q];
-            unpack4(q, k, P, f);
+            unpack8<S>(q, k, P, f);
             R ax, ay, az;
             psi_stencil<R>(lo, mid, hi, cin + k, SX, ax, ay, az);
             const R rho = rbuf[bs][nb + k];
@@ -1213,21 +1259,13 @@ __global__ void __launch_bounds__(2 * SPLIT_ROLE)
             collide<R, OP>(f, rho, mG_psi * ax + rho * P.gx, mG_psi * ay + rho * P.gy, mG_psi * az + rho * P.gz,
                            ax * ax + ay * ay + az * az, P);
 #pragma unroll
-            for (int a = 0; a < Q; ++a) {
-                const _Float16 h = (_Float16)fmaf(f[a], P.hs, -P.shh(a));
-                if (k == 0) plo[a].x = h;
-                else if (k == 1) plo[a].y = h;
-                else if (k == 2) phi[a].x = h;
-                else phi[a].y = h;
-            }
+            for (int a = 0; a < Q; ++a) out.put(k, a, f[a], P);
         }
         const uint32_t pz = __builtin_amdgcn_readfirstlane((uint32_t)c * PB);
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
             using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(bB.of(a), 0, 0, 0));
-            const unsigned long long w = (unsigned long long)__builtin_bit_cast(uint32_t, plo[a]) |
-                                         ((unsigned long long)__builtin_bit_cast(uint32_t, phi[a]) << 32);
-            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, w), bB.of(a), (int)oin.c,
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, out.word(a)), bB.of(a), (int)oin.c,
                                                   (int)u_so(bB, a, pz), LBM_BUF_STORE_AUX);
         }
     };
@@ -1235,16 +1273,21 @@ __global__ void __launch_bounds__(2 * SPLIT_ROLE)
     // Iteration i: pullers take plane zb - 1 + i (up to ze), colliders plane
     // zb - 3 + i (from zb to ze - 1).  Every thread runs every iteration and
     // its barrier.
+    // The roles run separate loops (each with its own registers live across
+    // iterations) that meet at the same number of barriers.
     const int iters = (ze - zb) + 3;
-    for (int i = 0; i < iters; ++i) {
-        if (puller) {
+    if (puller) {
+        for (int i = 0; i < iters; ++i) {
             const int p = zb - 1 + i;
             if (p <= ze) pull_plane(p);
-        } else {
+            lds_barrier();
+        }
+    } else {
+        for (int i = 0; i < iters; ++i) {
             const int c = zb - 3 + i;
             if (c >= zb) collide_plane(c);
+            lds_barrier();
         }
-        lds_barrier();
     }
 }
 

@@ -15,6 +15,7 @@ STEP_TILES = {
     ("two_droplets_256", "f64", "fused"): (128, 4, 128),
     ("two_droplets_256", "f32", "fused"): (64, 4, 128),
     ("two_droplets_256", "f32", "pairs"): (128, 8, 64),
+    ("two_droplets_256", "f32", "split"): (128, 4, 128),
     ("two_droplets_256", "f16s", "fused"): (64, 4, 32),
     ("two_droplets_256", "f16s", "pairs"): (128, 8, 64),
     ("two_droplets_256", "f16s", "quads"): (128, 16, 32),
@@ -26,7 +27,7 @@ STEP_TILES = {
 # Faster step kernel per (workload, storage); absent: "fused".
 STEP_MODES = {
     ("laplace_128", "f16s"): "pairs",
-    ("two_droplets_256", "f32"): "pairs",
+    ("two_droplets_256", "f32"): "split",
     ("two_droplets_256", "f16s"): "split",
     ("sessile_384x384x192", "f32"): "pairs",
 }

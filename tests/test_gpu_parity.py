@@ -156,7 +156,7 @@ def test_fp64_parity_500_steps_droplet_32():
         assert e < 1e-12, (s, e)
 
 
-@pytest.mark.parametrize("mode", ["fused", "pairs"])
+@pytest.mark.parametrize("mode", ["fused", "pairs", "split"])
 @pytest.mark.parametrize("op", ["nonorth", "orth"])
 @pytest.mark.parametrize("name", ["droplet_32", "ragged_70x37x21", "walls_40x33x19_60deg", "visc_two_droplets_48"])
 def test_fp32_parity(name, op, mode):
@@ -328,18 +328,22 @@ def test_quad_mode_bit_identical_to_fused(name, tile, op):
     assert np.array_equal(got, fused)
 
 
-SPLIT_CASES = [("ragged_68x37x21", (32, 4, 7)), ("ragged_68x37x21", (68, 8, 21)), ("walls_40x33x19_60deg", (40, 4, 7)),
-               ("droplet_32", (32, 8, 8)), ("visc_two_droplets_48", (16, 8, 12))]
+SPLIT_CASES = [("f16s", "ragged_68x37x21", (32, 4, 7)), ("f16s", "ragged_68x37x21", (68, 8, 21)),
+               ("f16s", "walls_40x33x19_60deg", (40, 4, 7)), ("f16s", "droplet_32", (32, 8, 8)),
+               ("f16s", "visc_two_droplets_48", (16, 8, 12)),
+               ("f32", "ragged_70x37x21", (32, 4, 7)), ("f32", "ragged_70x37x21", (70, 2, 21)),
+               ("f32", "walls_40x33x19_60deg", (40, 4, 7)), ("f32", "droplet_32", (32, 8, 8)),
+               ("f32", "visc_two_droplets_48", (16, 8, 12))]
 
 
 @pytest.mark.parametrize("op", ["nonorth", "orth"])
-@pytest.mark.parametrize("name,tile", SPLIT_CASES)
-def test_split_mode_bit_identical_to_fused(name, tile, op):
+@pytest.mark.parametrize("storage,name,tile", SPLIT_CASES)
+def test_split_mode_bit_identical_to_fused(storage, name, tile, op):
     """Pullers three planes ahead of colliders, planes handed over in LDS:
     the same populations as the one-node kernel."""
-    cfg, rho, u, ftile = _case(name, op, "f16s")
+    cfg, rho, u, ftile = _case(name, op, storage)
     fused = gpu_states(cfg, rho, u, [3], ftile, "fused")[0]
-    print(f"[gpu] split {name} f16s {op} tile={tile}", flush=True)
+    print(f"[gpu] split {name} {storage} {op} tile={tile}", flush=True)
     lat = Lattice(cfg)
     lat.set_step_mode("split").set_tile(*tile)
     lat.init_fields(rho, u).step(3)
@@ -348,9 +352,22 @@ def test_split_mode_bit_identical_to_fused(name, tile, op):
     assert np.array_equal(got, fused)
 
 
+def test_split_mode_two_column_lattice():
+    """FP32, nx = 2: one group per row, on the seam at both ends at once."""
+    cfg = li.params(2, 6, 5, T_over_Tc=0.8, storage="f32")
+    rho, u = li.random_fields(2, 6, 5, seed=13)
+    fused = gpu_states(cfg, rho, u, [2], (2, 6, 5), "fused")[0]
+    lat = Lattice(cfg)
+    lat.set_step_mode("split").set_tile(2, 6, 5)
+    lat.init_fields(rho, u).step(2)
+    got = lat.read_populations().cpu().numpy()
+    lat.close()
+    assert np.array_equal(got, fused)
+
+
 def test_split_mode_rejections():
     _need_gpu()
-    for shape, storage in [((32, 8, 8), "f32"), ((34, 8, 8), "f16s")]:
+    for shape, storage in [((32, 8, 8), "f64"), ((33, 8, 8), "f32"), ((34, 8, 8), "f16s")]:
         lat = Lattice(li.params(*shape, storage=storage))
         with pytest.raises(binding.LbmError) as e:
             lat.set_step_mode("split")
@@ -664,7 +681,8 @@ WRITE_CHECK_CASES = [("ragged_70x37x21", "f32", "fused", None), ("ragged_70x37x2
                      ("ragged_68x37x21", "f16s", "quads", (32, 4, 7)),
                      ("walls_40x33x19_60deg", "f16s", "quads", (40, 4, 7)),
                      ("ragged_68x37x21", "f16s", "split", (32, 4, 7)),
-                     ("walls_40x33x19_60deg", "f16s", "split", (40, 4, 7))]
+                     ("walls_40x33x19_60deg", "f16s", "split", (40, 4, 7)),
+                     ("ragged_70x37x21", "f32", "split", (32, 4, 7))]
 
 
 @pytest.mark.parametrize("name,storage,mode,tile", WRITE_CHECK_CASES)
