@@ -5,11 +5,13 @@ either kernel give the same populations; these are the fastest found."""
 STEP_TILES = {
     # (workload, storage, mode) -> (tx, ty, cz); mode "fused": one node per
     # thread, "pairs" / "quads": two / four x-adjacent nodes per thread, "split":
-    # four per thread with pulling and colliding waves (tx counts nodes)
+    # 8-byte groups (four F16S or two FP32 nodes) with pulling and colliding
+    # waves (tx counts nodes)
     ("droplet_32", "f64", "fused"): (32, 2, 4),
     ("laplace_128", "f64", "fused"): (128, 4, 16),
     ("laplace_128", "f32", "fused"): (64, 4, 16),
     ("laplace_128", "f32", "pairs"): (64, 8, 8),
+    ("laplace_128", "f32", "split"): (64, 8, 16),
     ("laplace_128", "f16s", "fused"): (64, 8, 16),
     ("laplace_128", "f16s", "pairs"): (64, 8, 8),
     ("two_droplets_256", "f64", "fused"): (128, 4, 128),
@@ -26,6 +28,7 @@ STEP_TILES = {
 
 # Faster step kernel per (workload, storage); absent: "fused".
 STEP_MODES = {
+    ("laplace_128", "f32"): "split",
     ("laplace_128", "f16s"): "pairs",
     ("two_droplets_256", "f32"): "split",
     ("two_droplets_256", "f16s"): "split",
