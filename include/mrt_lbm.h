@@ -288,15 +288,16 @@ lbm_status lbm_batch_status(lbm_batch *b, lbm_status *status);
 /* Number of runs in the batch (0 for NULL). */
 int32_t lbm_batch_runs(const lbm_batch *b);
 /* Persistent grid size (blocks), per-run tiles and step kernel (one or two
- * nodes per thread, where both apply) chosen by timing candidates;
+ * nodes per thread, or the split step, where they apply) chosen by timing candidates;
  * synchronises; state unchanged. */
 lbm_status lbm_batch_autotune(lbm_batch *b, int32_t trials, int32_t *best_blocks);
 lbm_status lbm_batch_set_blocks(lbm_batch *b, int32_t blocks);
-/* Step kernel of the batch: LBM_STEP_FUSED or LBM_STEP_PAIRS (two nodes per
- * thread; needs FP32/F16S storage and even nx in every run, else
- * LBM_ERR_UNSUPPORTED).  A new batch uses LBM_STEP_PAIRS where it applies.
- * Rebuilds the work list and drops captured graphs; results are bit for bit
- * the same in both modes. */
+/* Step kernel of the batch: LBM_STEP_FUSED, LBM_STEP_PAIRS (two nodes per
+ * thread; FP32/F16S storage and even nx in every run) or LBM_STEP_SPLIT
+ * (pulling and colliding waves; FP32 with even nx or F16S with nx a multiple
+ * of 4 in every run); otherwise LBM_ERR_UNSUPPORTED.  A new batch uses
+ * LBM_STEP_PAIRS where it applies.  Rebuilds the work list and drops captured
+ * graphs; results are bit for bit the same in all modes. */
 lbm_status lbm_batch_set_step_mode(lbm_batch *b, int32_t mode);
 lbm_status lbm_batch_get_step_mode(const lbm_batch *b, int32_t *mode);
 lbm_status lbm_batch_kernel_time(lbm_batch *b, double *avg_ms, int64_t *launches);

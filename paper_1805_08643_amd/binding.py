@@ -559,7 +559,7 @@ class Batch:
         _call("lbm_batch_set_blocks", _vp(self.h), int(blocks))
 
     def set_step_mode(self, mode):
-        """mode: "fused" or "pairs"."""
+        """mode: "fused", "pairs" or "split"."""
         _call("lbm_batch_set_step_mode", _vp(self.h), STEP_MODES[mode])
         return self
 

@@ -194,12 +194,17 @@ constexpr size_t kMaxStepLds = 65536;
 // The split kernel's LDS holds tiles of up to SPLIT_TX x SPLIT_TY nodes,
 // SPLIT_ROLE quads per role.
 lbm_status check_split_tile(const lbm_tile &t, int npt) {
-    if (t.tx < npt || t.ty < 1 || t.cz < 1 || t.tx % npt || t.tx > SPLIT_TX || t.ty > SPLIT_TY ||
-        (t.tx / npt) * t.ty > SPLIT_ROLE || t.tx * t.ty > SPLIT_NODES)
+    if (t.tx < npt || t.ty < 1 || t.cz < 1 || t.tx % npt || t.tx > SPLIT_TX || (t.tx / npt) * t.ty > SPLIT_ROLE ||
+        t.tx * t.ty > SPLIT_NODES || (t.tx + 2) * (t.ty + 2) > SPLIT_SP)
         return fail(LBM_ERR_INVALID_ARG, "split mode needs a tile width that is a multiple of %d and at most %d, at "
-                    "most %d rows and %d groups of %d nodes; got %d x %d x %d", npt, SPLIT_TX, SPLIT_TY,
-                    SPLIT_ROLE, npt, t.tx, t.ty, t.cz);
+                    "most %d groups of %d nodes, %d nodes, and (tx + 2)(ty + 2) <= %d; got %d x %d x %d", npt,
+                    SPLIT_TX, SPLIT_ROLE, npt, SPLIT_NODES, SPLIT_SP, t.tx, t.ty, t.cz);
     return LBM_OK;
+}
+
+// Most rows a split tile of width tx can have.
+int split_rows(int tx, int npt) {
+    return std::max(1, std::min({SPLIT_ROLE / (tx / npt), SPLIT_NODES / tx, SPLIT_SP / (tx + 2) - 2}));
 }
 
 lbm_status check_tile(const lbm_tile &t, int storage, int npt = 1) {
@@ -283,7 +288,7 @@ bool split_apply(const lbm_params &p) {
 lbm_tile split_tile(int nx, int ny, int nz, int npt) {
     lbm_tile t{};
     t.tx = std::min(SPLIT_TX, (nx + npt - 1) / npt * npt);
-    t.ty = std::max(1, std::min(std::min(ny, SPLIT_TY), SPLIT_ROLE / (t.tx / npt)));
+    t.ty = std::max(1, std::min({ny, SPLIT_TY, split_rows(t.tx, npt)}));
     const int ncol = ((nx + t.tx - 1) / t.tx) * ((ny + t.ty - 1) / t.ty);
     const int nzc = std::max(1, (256 + ncol - 1) / ncol);
     t.cz = std::max(std::min(nz, 8), (nz + nzc - 1) / nzc);
@@ -924,7 +929,7 @@ struct lbm_batch {
     size_t smem = 0;
     int parity = 0;
     int item_nodes = 8192;
-    bool pairs = false;  // two x-adjacent nodes per thread
+    int mode = LBM_STEP_FUSED;  // LBM_STEP_FUSED, LBM_STEP_PAIRS or LBM_STEP_SPLIT
     long long nodes = 0;
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;
@@ -937,8 +942,17 @@ struct lbm_batch {
 
 namespace {
 
-lbm_tile batch_tile(const lbm_params &p, int item_nodes, bool pairs) {
+lbm_tile batch_tile(const lbm_params &p, int item_nodes, int mode) {
     lbm_tile t{};
+    if (mode == LBM_STEP_SPLIT) {  // whole rows up to 128 nodes, as many rows as the LDS takes
+        const int npt = npt_of(mode, p.storage);
+        t.tx = std::min(SPLIT_TX, p.nx);
+        t.ty = std::max(1, std::min(p.ny, split_rows(t.tx, npt)));
+        const int cols = t.tx * t.ty;
+        t.cz = std::max(1, std::min(p.nz, (item_nodes + cols / 2) / cols));
+        return t;
+    }
+    const bool pairs = mode == LBM_STEP_PAIRS;
     if (pairs) t.tx = std::min(p.nx, 128);
     else if (p.nx <= 128) t.tx = p.nx;
     else t.tx = default_tile(p.nx, p.ny, p.nz).tx;
@@ -982,7 +996,7 @@ lbm_status batch_build(lbm_batch *b) {
     long long nodes = 0;
     for (size_t k = 0; k < b->runs.size(); ++k) {
         lbm_ctx *c = b->runs[k];
-        c->tile = batch_tile(c->p, b->item_nodes, b->pairs);
+        c->tile = batch_tile(c->p, b->item_nodes, b->mode);
         fill_grid(c->g, c->p, c->tile);
         RunDesc &d = b->desc[k];
         d.g = c->g;
@@ -991,8 +1005,9 @@ lbm_status batch_build(lbm_batch *b) {
         d.offB = b->run_off[k] + c->L.B;
         d.tile_begin = tiles;
         tiles += c->g.ntiles;
-        threads = std::max(threads, block_threads(c->g.tx, c->g.ty, b->pairs ? 2 : 1));
-        smem = std::max(smem, step_smem(c, c->g));
+        threads = b->mode == LBM_STEP_SPLIT ? 2 * SPLIT_ROLE
+                                            : std::max(threads, block_threads(c->g.tx, c->g.ty, npt_of(b->mode, b->storage)));
+        smem = b->mode == LBM_STEP_SPLIT ? 0 : std::max(smem, step_smem(c, c->g));
         nodes += c->g.N;
     }
     b->total_tiles = tiles;
@@ -1010,8 +1025,20 @@ lbm_status batch_build(lbm_batch *b) {
 lbm_status batch_launch(lbm_batch *b, hipStream_t st, int parity, int blocks) {
     const RunDesc *d = reinterpret_cast<const RunDesc *>(b->ws + b->desc_off);
     const int nr = (int)b->runs.size();
+#define LBM_SCASE(s, o)                                                                                       \
+    if (b->storage == s && b->op == o && b->mode == LBM_STEP_SPLIT) {                                         \
+        hipLaunchKernelGGL((k_batch_split<s, o>), dim3(blocks), dim3(2 * SPLIT_ROLE), 0, st, b->ws, d, nr,      \
+                           b->total_tiles, parity);                                                           \
+        HIP_TRY(hipGetLastError());                                                                           \
+        return LBM_OK;                                                                                        \
+    }
+    LBM_SCASE(ST_F32, OP_NONORTH)
+    LBM_SCASE(ST_F32, OP_ORTH)
+    LBM_SCASE(ST_F16S, OP_NONORTH)
+    LBM_SCASE(ST_F16S, OP_ORTH)
+#undef LBM_SCASE
 #define LBM_BCASE(s, o, pr)                                                                                   \
-    if (b->storage == s && b->op == o && b->pairs == pr) {                                                    \
+    if (b->storage == s && b->op == o && (b->mode == LBM_STEP_PAIRS) == pr && b->mode != LBM_STEP_SPLIT) {     \
         hipLaunchKernelGGL((k_batch_step<s, o, pr>), dim3(blocks), dim3(b->threads), b->smem, st, b->ws, d, nr, \
                            b->total_tiles, parity);                                                           \
         HIP_TRY(hipGetLastError());                                                                           \
@@ -1037,9 +1064,16 @@ bool batch_pairs_apply(const lbm_params *runs, int n) {
     return true;
 }
 
+bool batch_split_apply(const lbm_batch *b) {
+    for (lbm_ctx *c : b->runs)
+        if (!split_apply(c->p)) return false;
+    return true;
+}
+
 int default_blocks(const lbm_batch *b) {
-    // Persistent grid: a few blocks per CU, never more blocks than items.
-    return std::max(1, std::min(b->total_tiles, 256 * 4));
+    // Persistent grid: a few blocks per CU (one with the split step's LDS),
+    // never more blocks than items.
+    return std::max(1, std::min(b->total_tiles, b->mode == LBM_STEP_SPLIT ? 256 : 256 * 4));
 }
 
 void batch_advance(lbm_batch *b, int64_t n) {
@@ -1098,7 +1132,7 @@ lbm_status lbm_batch_create(const lbm_params *runs, int32_t n, void *dev_ws, siz
     b->stream = static_cast<hipStream_t>(hip_stream);
     b->op = runs[0].op;
     b->storage = runs[0].storage;
-    b->pairs = batch_pairs_apply(runs, n);
+    b->mode = batch_pairs_apply(runs, n) ? LBM_STEP_PAIRS : LBM_STEP_FUSED;
     for (int k = 0; k < n; ++k) {
         lbm_ctx *c = nullptr;
         s = lbm_create(&runs[k], b->ws + b->run_off[k], layout_of(runs[k]).total, hip_stream, &c);
@@ -1247,23 +1281,26 @@ lbm_status lbm_batch_set_blocks(lbm_batch *b, int32_t blocks) {
 
 lbm_status lbm_batch_set_step_mode(lbm_batch *b, int32_t mode) {
     if (!b) return fail(LBM_ERR_INVALID_ARG, "batch is NULL");
-    if (mode != LBM_STEP_FUSED && mode != LBM_STEP_PAIRS)
-        return fail(LBM_ERR_INVALID_ARG, "batched runs take LBM_STEP_FUSED or LBM_STEP_PAIRS, got %d", mode);
+    if (mode != LBM_STEP_FUSED && mode != LBM_STEP_PAIRS && mode != LBM_STEP_SPLIT)
+        return fail(LBM_ERR_INVALID_ARG, "batched runs take LBM_STEP_FUSED, LBM_STEP_PAIRS or LBM_STEP_SPLIT, got %d",
+                    mode);
     if (mode == LBM_STEP_PAIRS) {
         for (size_t k = 0; k < b->runs.size(); ++k)
             if (!pairs_apply(b->runs[k]->p))
                 return fail(LBM_ERR_UNSUPPORTED, "run %zu: pair mode needs FP32/F16S storage and even nx", k);
     }
-    b->pairs = mode == LBM_STEP_PAIRS;
+    if (mode == LBM_STEP_SPLIT && !batch_split_apply(b))
+        return fail(LBM_ERR_UNSUPPORTED, "split mode needs FP32 with even nx or F16S with nx a multiple of 4 in every run");
+    b->mode = mode;
     lbm_status s = batch_build(b);
     if (s) return s;
-    b->blocks = std::min(b->blocks, b->total_tiles);
+    b->blocks = std::min(mode == LBM_STEP_SPLIT ? 256 : b->blocks, b->total_tiles);
     return LBM_OK;
 }
 
 lbm_status lbm_batch_get_step_mode(const lbm_batch *b, int32_t *mode) {
     if (!b || !mode) return fail(LBM_ERR_INVALID_ARG, "null argument");
-    *mode = b->pairs ? LBM_STEP_PAIRS : LBM_STEP_FUSED;
+    *mode = b->mode;
     return LBM_OK;
 }
 
@@ -1276,20 +1313,22 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t trials, int32_t *best_blocks
     const int items[] = {4096, 8192, 16384, 32768};
     float best = 1e30f;
     int best_items = b->item_nodes, best_blk = b->blocks;
-    bool best_pairs = b->pairs;
-    std::vector<bool> modes{false};
+    int best_mode = b->mode;
+    std::vector<int> modes{LBM_STEP_FUSED};
     bool all_pairs = true;
     for (lbm_ctx *c : b->runs) all_pairs = all_pairs && pairs_apply(c->p);
-    if (all_pairs) modes.push_back(true);
+    if (all_pairs) modes.push_back(LBM_STEP_PAIRS);
+    if (batch_split_apply(b)) modes.push_back(LBM_STEP_SPLIT);
     lbm_status s;
-    for (bool pr : modes)
+    for (int md : modes)
     for (int it : items) {
-        b->pairs = pr;
+        b->mode = md;
         b->item_nodes = it;
         if ((s = batch_build(b))) return s;
         const int cands[] = {256, 512, 1024, 2048, 4096, b->total_tiles};
         for (int blk : cands) {
             if (blk > b->total_tiles) continue;
+            if (md == LBM_STEP_SPLIT && blk > 256 && blk != b->total_tiles) continue;  // one block per CU
             // Steps write the other buffer of every run only: state unchanged.
             if ((s = batch_launch(b, b->stream, b->parity, blk))) return s;
             HIP_TRY(hipEventRecord(e0, b->stream));
@@ -1303,13 +1342,13 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t trials, int32_t *best_blocks
                 best = ms;
                 best_items = it;
                 best_blk = blk;
-                best_pairs = pr;
+                best_mode = md;
             }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    b->pairs = best_pairs;
+    b->mode = best_mode;
     b->item_nodes = best_items;
     if ((s = batch_build(b))) return s;
     b->blocks = best_blk;

@@ -1107,21 +1107,23 @@ constexpr int SPLIT_TX = 128, SPLIT_TY = 8, SPLIT_ROLE = 256;  // max tile width
 constexpr int SPLIT_SP = (SPLIT_TY + 2) * (SPLIT_TX + 2);     // psi ring slot
 constexpr int SPLIT_NODES = 1024;                               // max nodes per tile plane
 
+struct SplitLds {
+    unsigned long long qbuf[3][Q][SPLIT_ROLE];  // populations of three planes, one group per slot
+    float rbuf[3][SPLIT_NODES];                 // densities of three planes
+    float ring[4][SPLIT_SP];                    // psi ring
+};
+
+// One tile of the split step; every thread of the 512-thread block calls it.
 template <int S, int OP, bool WALL>
-__global__ void __launch_bounds__(2 * SPLIT_ROLE)
-    k_step_split(const typename Storage<S>::T *__restrict__ A, typename Storage<S>::T *__restrict__ B,
-                 const float *__restrict__ gpsi, GridDesc g, PhysD pd) {
+__device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, typename Storage<S>::T *__restrict__ B,
+                                  const float *__restrict__ gpsi, const GridDesc &g, const Phys<float> &P, int tile,
+                                  SplitLds &L) {
     using R = float;
     using T = typename Storage<S>::T;
     constexpr int NPT = Lane8<S>::NPT;
-    __shared__ unsigned long long qbuf[3][Q][SPLIT_ROLE];  // populations of three planes, one group per slot
-    __shared__ float rbuf[3][SPLIT_NODES];                 // densities of three planes
-    __shared__ float ring[4][SPLIT_SP];                    // psi ring
-    const int tile = xcd_tile(blockIdx.x, g.per_xcd);
-    if (tile >= g.ntiles) return;
-    Phys<R> P;
-    P.load(pd);
-
+    auto &qbuf = L.qbuf;
+    auto &rbuf = L.rbuf;
+    auto &ring = L.ring;
     const int TX = g.tx, TY = g.ty, TXG = g.tx / NPT;
     const int SX = TX + 2;
     int t = tile;
@@ -1291,6 +1293,18 @@ __global__ void __launch_bounds__(2 * SPLIT_ROLE)
     }
 }
 
+template <int S, int OP, bool WALL>
+__global__ void __launch_bounds__(2 * SPLIT_ROLE)
+    k_step_split(const typename Storage<S>::T *__restrict__ A, typename Storage<S>::T *__restrict__ B,
+                 const float *__restrict__ gpsi, GridDesc g, PhysD pd) {
+    __shared__ SplitLds lds;
+    const int tile = xcd_tile(blockIdx.x, g.per_xcd);
+    if (tile >= g.ntiles) return;
+    Phys<float> P;
+    P.load(pd);
+    tile_split<S, OP, WALL>(A, B, gpsi, g, P, tile, lds);
+}
+
 // ---------------------------------------------------------------------------
 // Single-phase step with walls on any axis (the lid-driven cavity of
 // Appendix B): no pseudopotential, one node per thread; the body force is
@@ -1362,6 +1376,35 @@ __global__ void LBM_STEP_ATTR
         else
             tile_march<S, OP, false>(src, dst, nullptr, g, P, item - rd.tile_begin, ps);
         lds_barrier();  // the next item reuses the LDS ring
+    }
+}
+
+// Batched runs with the split step: the same work list, one 512-thread
+// block per compute unit (the split step's LDS).
+template <int S, int OP>
+__global__ void __launch_bounds__(2 * SPLIT_ROLE)
+    k_batch_split(unsigned char *__restrict__ ws, const RunDesc *__restrict__ runs, int nruns, int total_tiles,
+                  int parity) {
+    using T = typename Storage<S>::T;
+    __shared__ SplitLds lds;
+    const int per_xcd = (total_tiles + 7) / 8;
+    const int nvirt = 8 * per_xcd;
+    for (int v = blockIdx.x; v < nvirt; v += gridDim.x) {
+        const int item = xcd_tile(v, per_xcd);
+        if (item >= total_tiles) continue;
+        int lo = 0, hi = nruns - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (runs[mid].tile_begin <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const RunDesc &rd = runs[lo];
+        const GridDesc g = rd.g;
+        Phys<float> P;
+        P.load(rd.pd);
+        const T *src = reinterpret_cast<const T *>(ws + (parity ? rd.offB : rd.offA));
+        T *dst = reinterpret_cast<T *>(ws + (parity ? rd.offA : rd.offB));
+        tile_split<S, OP, false>(src, dst, nullptr, g, P, item - rd.tile_begin, lds);
     }
 }
 

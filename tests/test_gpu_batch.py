@@ -74,13 +74,13 @@ def test_batch_bit_identical_to_single_lattices(storage):
 
 @pytest.mark.parametrize("storage", ["f32", "f16s"])
 def test_batch_step_modes_bit_identical(storage):
-    """Two nodes per thread (default for even sizes) and one node per thread
-    give the same populations in a batch."""
+    """Two nodes per thread (default for even sizes), one node per thread and
+    the split step give the same populations in a batch."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     runs = _runs(storage, sizes=(32, 48, 20, 36))
     out = {}
-    for mode in ("pairs", "fused"):
+    for mode in ("pairs", "fused", "split"):
         b = Batch([r[0] for r in runs])
         assert b.step_mode() == "pairs"
         b.set_step_mode(mode)
@@ -92,6 +92,20 @@ def test_batch_step_modes_bit_identical(storage):
         b.close()
     for k in range(len(runs)):
         assert np.array_equal(out["pairs"][k], out["fused"][k]), k
+        assert np.array_equal(out["pairs"][k], out["split"][k]), k
+
+
+def test_batch_split_rejects_unsuitable_runs():
+    """F16S split needs nx % 4 == 0 in every run."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    runs = _runs("f16s", sizes=(32, 18))
+    b = Batch([r[0] for r in runs])
+    with pytest.raises(binding.LbmError) as e:
+        b.set_step_mode("split")
+    assert e.value.status == -5
+    assert b.step_mode() == "pairs"
+    b.close()
 
 
 def test_batch_full_workload_sampled_runs():
