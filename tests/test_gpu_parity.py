@@ -375,7 +375,8 @@ def test_split_mode_rejections():
         lat.close()
     lat = Lattice(li.params(32, 32, 8, storage="f16s"))
     lat.set_step_mode("split")
-    for tile in [(30, 4, 4), (32, 16, 4), (256, 1, 4)]:
+    lat.set_tile(32, 32, 4)  # 256 groups of four: the LDS limit
+    for tile in [(30, 4, 4), (32, 40, 4), (128, 9, 4), (256, 1, 4)]:
         with pytest.raises(binding.LbmError) as e:
             lat.set_tile(*tile)
         assert e.value.status == -1, tile
