@@ -494,15 +494,20 @@ def test_save_load_resume_is_bit_identical(storage):
     b.close()
 
 
-def test_autotune_leaves_state_unchanged():
+@pytest.mark.parametrize("storage,mode", [("f32", "pairs"), ("f32", "split"), ("f16s", "split"), ("f64", "fused")])
+def test_autotune_leaves_state_unchanged(storage, mode):
+    """The autotuner times candidate tiles of the current step mode by
+    writing the other buffer only, and keeps a tile valid for that mode."""
     _need_gpu()
     cfg, init = li.c1_droplet()
-    cfg = dict(cfg, storage="f32")
+    cfg = dict(cfg, storage=storage, rho_ref=init["rho_V"], f16_exp=f16_exp_for(1.25 * init["rho_L"]))
     lat = Lattice(cfg)
+    lat.set_step_mode(mode)
     lat.init_droplets(init["droplets"], init["rho_L"], init["rho_V"], init["W"]).step(2)
     f0 = lat.read_populations().cpu().numpy()
     t = lat.autotune(trials=1)
     assert lat.get_tile() == t
+    lat.set_tile(*t)  # valid for the mode
     f1 = lat.read_populations().cpu().numpy()
     assert np.array_equal(f0, f1)
     lat.step(1)
