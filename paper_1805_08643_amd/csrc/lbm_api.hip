@@ -194,17 +194,21 @@ constexpr size_t kMaxStepLds = 65536;
 // The split kernel's LDS holds tiles of up to SPLIT_TX x SPLIT_TY nodes,
 // SPLIT_ROLE quads per role.
 lbm_status check_split_tile(const lbm_tile &t, int npt) {
+    // The halo ring, 2 (tx + 2) + 2 ty nodes, takes one node per thread of the block.
     if (t.tx < npt || t.ty < 1 || t.cz < 1 || t.tx % npt || t.tx > SPLIT_TX || (t.tx / npt) * t.ty > SPLIT_ROLE ||
-        t.tx * t.ty > SPLIT_NODES || (t.tx + 2) * (t.ty + 2) > SPLIT_SP)
+        t.tx * t.ty > SPLIT_NODES || (t.tx + 2) * (t.ty + 2) > SPLIT_SP || t.tx + t.ty + 2 > SPLIT_ROLE)
         return fail(LBM_ERR_INVALID_ARG, "split mode needs a tile width that is a multiple of %d and at most %d, at "
-                    "most %d groups of %d nodes, %d nodes, and (tx + 2)(ty + 2) <= %d; got %d x %d x %d", npt,
-                    SPLIT_TX, SPLIT_ROLE, npt, SPLIT_NODES, SPLIT_SP, t.tx, t.ty, t.cz);
+                    "most %d groups of %d nodes, %d nodes, (tx + 2)(ty + 2) <= %d and tx + ty <= %d; got %d x %d x %d",
+                    npt, SPLIT_TX, SPLIT_ROLE, npt, SPLIT_NODES, SPLIT_SP, SPLIT_ROLE - 2, t.tx, t.ty, t.cz);
     return LBM_OK;
 }
 
+// Whether a split tile's halo ring has more nodes than the pulling threads.
+bool split_ring2(int tx, int ty) { return 2 * (tx + 2) + 2 * ty > SPLIT_ROLE; }
+
 // Most rows a split tile of width tx can have.
 int split_rows(int tx, int npt) {
-    return std::max(1, std::min({SPLIT_ROLE / (tx / npt), SPLIT_NODES / tx, SPLIT_SP / (tx + 2) - 2}));
+    return std::max(1, std::min({SPLIT_ROLE / (tx / npt), SPLIT_NODES / tx, SPLIT_SP / (tx + 2) - 2, SPLIT_ROLE - 2 - tx}));
 }
 
 lbm_status check_tile(const lbm_tile &t, int storage, int npt = 1) {
@@ -386,13 +390,22 @@ lbm_status launch_step(lbm_ctx *c, const GridDesc &g, const void *src, void *dst
         }
         const unsigned grid = 8u * (unsigned)g.per_xcd;
         const int threads = block_threads(g.tx, g.ty, npt);
+        if (c->mode != LBM_STEP_SPLIT && threads > STEP_MAX_THREADS)
+            return fail(LBM_ERR_INVALID_ARG, "tile %d x %d at %d node(s) per thread needs %d threads, more than %d",
+                        g.tx, g.ty, npt, threads, STEP_MAX_THREADS);
         if (c->mode == LBM_STEP_SPLIT) {
             if constexpr (S.value != ST_F64) {
                 lbm_tile t{g.tx, g.ty, g.cz, 0};
                 if (g.nx % npt) return fail(LBM_ERR_INVALID_ARG, "split mode needs nx a multiple of %d", npt);
                 if (lbm_status e = check_split_tile(t, npt)) return e;
-                hipLaunchKernelGGL((k_step_split<S.value, O.value, W.value>), dim3(grid), dim3(2 * SPLIT_ROLE), 0,
-                                   c->stream, (const T *)src, (T *)dst, (const R *)c->gpsi(), g, c->pd);
+                if (split_ring2(g.tx, g.ty))
+                    hipLaunchKernelGGL((k_step_split<S.value, O.value, W.value, true>), dim3(grid),
+                                       dim3(2 * SPLIT_ROLE), 0, c->stream, (const T *)src, (T *)dst,
+                                       (const R *)c->gpsi(), g, c->pd);
+                else
+                    hipLaunchKernelGGL((k_step_split<S.value, O.value, W.value, false>), dim3(grid),
+                                       dim3(2 * SPLIT_ROLE), 0, c->stream, (const T *)src, (T *)dst,
+                                       (const R *)c->gpsi(), g, c->pd);
                 HIP_TRY(hipGetLastError());
                 return LBM_OK;
             } else {
@@ -850,9 +863,11 @@ lbm_status lbm_set_step_mode(lbm_ctx *c, int32_t mode, int32_t slab_planes) {
             c->tile = split_tile(c->p.nx, c->p.ny, c->p.nz, npt);
             fill_grid(c->g, c->p, c->tile);
         }
-    } else if (npt > 1 && check_tile(c->tile, c->p.storage, npt) != LBM_OK) {
+    } else if (check_tile(c->tile, c->p.storage, npt) != LBM_OK) {
+        // The tile of the previous mode need not suit this one (a pair tile
+        // 128 nodes wide needs 1024 threads at one node per thread).
         g_err.clear();
-        c->tile = wide_tile(c->p.nx, c->p.ny, c->p.nz, npt);
+        c->tile = npt > 1 ? wide_tile(c->p.nx, c->p.ny, c->p.nz, npt) : default_tile(c->p.nx, c->p.ny, c->p.nz);
         fill_grid(c->g, c->p, c->tile);
     }
     c->mode = mode;
@@ -930,6 +945,7 @@ struct lbm_batch {
     int parity = 0;
     int item_nodes = 8192;
     int mode = LBM_STEP_FUSED;  // LBM_STEP_FUSED, LBM_STEP_PAIRS or LBM_STEP_SPLIT
+    bool ring2 = false;         // split: some run's tile has a halo ring beyond the pullers
     long long nodes = 0;
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;
@@ -990,6 +1006,7 @@ size_t batch_total(const lbm_params *runs, int32_t n, std::vector<size_t> *offs,
 
 lbm_status batch_build(lbm_batch *b) {
     b->desc.assign(b->runs.size(), RunDesc{});
+    b->ring2 = false;
     int tiles = 0;
     int threads = 64;
     size_t smem = 0;
@@ -1005,6 +1022,7 @@ lbm_status batch_build(lbm_batch *b) {
         d.offB = b->run_off[k] + c->L.B;
         d.tile_begin = tiles;
         tiles += c->g.ntiles;
+        if (b->mode == LBM_STEP_SPLIT && split_ring2(c->g.tx, c->g.ty)) b->ring2 = true;
         threads = b->mode == LBM_STEP_SPLIT ? 2 * SPLIT_ROLE
                                             : std::max(threads, block_threads(c->g.tx, c->g.ty, npt_of(b->mode, b->storage)));
         smem = b->mode == LBM_STEP_SPLIT ? 0 : std::max(smem, step_smem(c, c->g));
@@ -1025,17 +1043,21 @@ lbm_status batch_build(lbm_batch *b) {
 lbm_status batch_launch(lbm_batch *b, hipStream_t st, int parity, int blocks) {
     const RunDesc *d = reinterpret_cast<const RunDesc *>(b->ws + b->desc_off);
     const int nr = (int)b->runs.size();
-#define LBM_SCASE(s, o)                                                                                       \
-    if (b->storage == s && b->op == o && b->mode == LBM_STEP_SPLIT) {                                         \
-        hipLaunchKernelGGL((k_batch_split<s, o>), dim3(blocks), dim3(2 * SPLIT_ROLE), 0, st, b->ws, d, nr,      \
+#define LBM_SCASE(s, o, r2)                                                                                   \
+    if (b->storage == s && b->op == o && b->mode == LBM_STEP_SPLIT && b->ring2 == r2) {                       \
+        hipLaunchKernelGGL((k_batch_split<s, o, r2>), dim3(blocks), dim3(2 * SPLIT_ROLE), 0, st, b->ws, d, nr,  \
                            b->total_tiles, parity);                                                           \
         HIP_TRY(hipGetLastError());                                                                           \
         return LBM_OK;                                                                                        \
     }
-    LBM_SCASE(ST_F32, OP_NONORTH)
-    LBM_SCASE(ST_F32, OP_ORTH)
-    LBM_SCASE(ST_F16S, OP_NONORTH)
-    LBM_SCASE(ST_F16S, OP_ORTH)
+    LBM_SCASE(ST_F32, OP_NONORTH, false)
+    LBM_SCASE(ST_F32, OP_ORTH, false)
+    LBM_SCASE(ST_F16S, OP_NONORTH, false)
+    LBM_SCASE(ST_F16S, OP_ORTH, false)
+    LBM_SCASE(ST_F32, OP_NONORTH, true)
+    LBM_SCASE(ST_F32, OP_ORTH, true)
+    LBM_SCASE(ST_F16S, OP_NONORTH, true)
+    LBM_SCASE(ST_F16S, OP_ORTH, true)
 #undef LBM_SCASE
 #define LBM_BCASE(s, o, pr)                                                                                   \
     if (b->storage == s && b->op == o && (b->mode == LBM_STEP_PAIRS) == pr && b->mode != LBM_STEP_SPLIT) {     \

@@ -1114,7 +1114,8 @@ struct SplitLds {
 };
 
 // One tile of the split step; every thread of the 512-thread block calls it.
-template <int S, int OP, bool WALL>
+// RING2: the tile's halo ring has more nodes than there are pulling threads.
+template <int S, int OP, bool WALL, bool RING2>
 __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, typename Storage<S>::T *__restrict__ B,
                                   const float *__restrict__ gpsi, const GridDesc &g, const Phys<float> &P, int tile,
                                   SplitLds &L) {
@@ -1160,17 +1161,23 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
     NbOff8<S> oin;
     oin.set(gx, wl, wr, gy, wrapi(gy - 1, ny), wrapi(gy + 1, ny), nx);
 
-    // Halo ring: nh <= 2 * SPLIT_ROLE nodes, at most two per puller.
+    // Halo ring: nh <= 2 * SPLIT_ROLE nodes.  Each puller takes node rid and,
+    // without RING2, node rid + SPLIT_ROLE in a second round; with RING2 (a
+    // ring larger than the pullers, 20 nodes more for a 128-wide tile) the
+    // colliders take those after their collision, where they have time to
+    // spare.  Each form measured fastest where it is used, and without RING2
+    // the colliders' loop carries no halo code at all.
+    constexpr int HR = RING2 ? 1 : 2;  // halo rounds of a puller
     const int nh = 2 * SX + 2 * TY;
     int chl[2], hxs[2], hys[2];
     bool halo[2];
     NbOff oh[2];
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-        const int h = rid + r * SPLIT_ROLE;
+        const int h = puller ? rid + r * SPLIT_ROLE : rid + SPLIT_ROLE;
         int hlx = -1, hly = -1;
         halo[r] = false;
-        if (puller && h < nh) {
+        if ((puller ? r < HR : RING2 && r == 0) && h < nh) {
             if (h < SX) {
                 hlx = h - 1;
                 hly = -1;
@@ -1192,13 +1199,15 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
         oh[r].set(hxs[r], wrapi(hxs[r] - 1, nx), wrapi(hxs[r] + 1, nx), hys[r], wrapi(hys[r] - 1, ny),
                   wrapi(hys[r] + 1, ny), nx, E);
     }
+    // Colliding waves with a halo node (wave-uniform).
+    const bool chw = RING2 && !puller && (int)__builtin_amdgcn_readfirstlane(rid) + SPLIT_ROLE < nh;
     auto zwrap = [&](int zp) { return WALL ? zp : wrapi(zp, nz); };
     auto rslot = [&](int z) { return ring[(z - zb + 1) & 3]; };
     auto bslot = [&](int z) { return (z - zb + 3) % 3; };
 
-    // Puller: plane p into the LDS buffers.  (Issuing the next plane's loads
-    // before the barrier, to keep them in flight while it waits, measured
-    // slower.)
+    // Puller: plane p into the LDS buffers.  (Keeping the next plane's loads
+    // in flight as well, or issuing the halo node's loads together with the
+    // interior group's, measured slower on the tiles that fit the LDS best.)
     auto pull_plane = [&](int p) {
         R *slot = rslot(p);
         if (WALL && (p < 0 || p >= nz)) {
@@ -1208,7 +1217,7 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
                 for (int k = 0; k < NPT; ++k) slot[cin + k] = gp[(size_t)gy * nx + gx + k];
             }
 #pragma unroll
-            for (int r = 0; r < 2; ++r)
+            for (int r = 0; r < HR; ++r)
                 if (halo[r]) slot[chl[r]] = gp[(size_t)hys[r] * nx + hxs[r]];
             return;
         }
@@ -1218,7 +1227,7 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
         load8<S, WALL>(bA, nz, PB, pw, oin, q, sm);
         // The halo node's loads are consumed in the branch that issued them.
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
+        for (int r = 0; r < HR; ++r) {
             if (halo[r]) {
                 R fh[Q];
                 pull<S, WALL>(bA, nz, PB, pw, oh[r], P, fh);
@@ -1240,6 +1249,19 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
             if (need_in) slot[cin + k] = psi;
             if (active) rbuf[bs][nb + k] = rho;
         }
+    };
+    // Collider's share of the halo ring of plane p (RING2).
+    auto halo_plane = [&](int p) {
+        R *slot = rslot(p);
+        if (WALL && (p < 0 || p >= nz)) {
+            const R *gp = gpsi + (p < 0 ? 0 : (size_t)nx * ny);
+            if (halo[0]) slot[chl[0]] = gp[(size_t)hys[0] * nx + hxs[0]];
+            return;
+        }
+        R fh[Q];
+        pull<S, WALL>(bA, nz, PB, zwrap(p), oh[0], P, fh);
+        const R psh = pseudo_psi<R>(P, sum19<R>(fh));
+        if (halo[0]) slot[chl[0]] = psh;
     };
     // Collider: plane c from the LDS buffers to B.
     auto collide_plane = [&](int c) {
@@ -1288,12 +1310,15 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
         for (int i = 0; i < iters; ++i) {
             const int c = zb - 3 + i;
             if (c >= zb) collide_plane(c);
+            if constexpr (RING2) {
+                if (chw && c + 2 <= ze) halo_plane(c + 2);
+            }
             lds_barrier();
         }
     }
 }
 
-template <int S, int OP, bool WALL>
+template <int S, int OP, bool WALL, bool RING2>
 __global__ void __launch_bounds__(2 * SPLIT_ROLE)
     k_step_split(const typename Storage<S>::T *__restrict__ A, typename Storage<S>::T *__restrict__ B,
                  const float *__restrict__ gpsi, GridDesc g, PhysD pd) {
@@ -1302,7 +1327,7 @@ __global__ void __launch_bounds__(2 * SPLIT_ROLE)
     if (tile >= g.ntiles) return;
     Phys<float> P;
     P.load(pd);
-    tile_split<S, OP, WALL>(A, B, gpsi, g, P, tile, lds);
+    tile_split<S, OP, WALL, RING2>(A, B, gpsi, g, P, tile, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1381,7 +1406,7 @@ __global__ void LBM_STEP_ATTR
 
 // Batched runs with the split step: the same work list, one 512-thread
 // block per compute unit (the split step's LDS).
-template <int S, int OP>
+template <int S, int OP, bool RING2>
 __global__ void __launch_bounds__(2 * SPLIT_ROLE)
     k_batch_split(unsigned char *__restrict__ ws, const RunDesc *__restrict__ runs, int nruns, int total_tiles,
                   int parity) {
@@ -1404,7 +1429,7 @@ __global__ void __launch_bounds__(2 * SPLIT_ROLE)
         P.load(rd.pd);
         const T *src = reinterpret_cast<const T *>(ws + (parity ? rd.offB : rd.offA));
         T *dst = reinterpret_cast<T *>(ws + (parity ? rd.offA : rd.offB));
-        tile_split<S, OP, false>(src, dst, nullptr, g, P, item - rd.tile_begin, lds);
+        tile_split<S, OP, false, RING2>(src, dst, nullptr, g, P, item - rd.tile_begin, lds);
     }
 }
 

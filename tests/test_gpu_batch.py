@@ -95,6 +95,35 @@ def test_batch_step_modes_bit_identical(storage):
         assert np.array_equal(out["pairs"][k], out["split"][k]), k
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16s"])
+def test_batch_split_wide_run(storage):
+    """A run 132 nodes wide takes 128-wide split tiles, whose halo ring is
+    larger than the pulling waves: the batch launches the variant in which
+    colliding waves take the rest of the ring, also for the small runs."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    runs = _runs(storage, sizes=(20, 24))
+    p, init = runs[0]
+    wide = dict(p, nx=132, ny=12, nz=10)
+    init = dict(init, droplets=[dict(center=(66, 6, 5), r0=4.0)])
+    runs = [(wide, init)] + runs
+    print(f"[gpu] batch split wide {storage} runs={[(r[0]['nx'], r[0]['ny'], r[0]['nz']) for r in runs]}", flush=True)
+    b = Batch([r[0] for r in runs])
+    b.set_step_mode("split")
+    for k, (q, i) in enumerate(runs):
+        b.init_fields(k, *li.init_fields(q, i))
+    b.step(4, 3)
+    for k, (q, i) in enumerate(runs):
+        lat = Lattice(q)
+        lat.set_step_mode("fused")
+        lat.init_fields(*li.init_fields(q, i)).step(4)
+        got = b.pops(k)
+        assert np.isfinite(got).all(), k
+        assert np.array_equal(got, lat.read_populations().cpu().numpy()), k
+        lat.close()
+    b.close()
+
+
 def test_batch_split_rejects_unsuitable_runs():
     """F16S split needs nx % 4 == 0 in every run."""
     if not torch.cuda.is_available():

@@ -352,6 +352,56 @@ def test_split_mode_bit_identical_to_fused(storage, name, tile, op):
     assert np.array_equal(got, fused)
 
 
+# Tiles whose halo ring has more nodes than the pulling waves have threads:
+# the colliding waves take the rest.  (storage, lattice, tile, walls)
+SPLIT_RING_CASES = [("f16s", (132, 21, 9), (128, 8, 9), 0),  # 276-node ring, 20 on a colliding wave
+                    ("f32", (132, 13, 9), (128, 4, 9), 1),   # 268, walls in z
+                    ("f16s", (8, 210, 6), (4, 200, 6), 1),   # 412
+                    ("f32", (6, 260, 5), (2, 252, 5), 0)]    # 512: one node for every thread of the block
+
+
+@pytest.mark.parametrize("storage,shape,tile,walls", SPLIT_RING_CASES)
+def test_split_mode_halo_ring_beyond_pullers(storage, shape, tile, walls):
+    kw = dict(T_over_Tc=0.8, storage=storage, wall_z=walls)
+    if walls:
+        kw["theta_wall_deg"] = 60.0
+    if storage == "f16s":
+        kw.update(rho_ref=0.02, f16_exp=f16_exp_for(0.4))
+    cfg = li.params(*shape, **kw)
+    # A narrow density range keeps the Eq. (57) ghost layer below the C-S
+    # singularity at rho = 4 / b, so psi stays finite at the walls.
+    rho, u = li.random_fields(*shape, seed=17, rho_lo=0.15, rho_hi=0.25)
+    fused = gpu_states(cfg, rho, u, [3], (min(shape[0], 32), 4, shape[2]), "fused")[0]
+    assert np.isfinite(fused).all()
+    print(f"[gpu] split ring {storage} {shape} tile={tile} walls={walls}", flush=True)
+    lat = Lattice(cfg)
+    lat.set_step_mode("split").set_tile(*tile)
+    lat.init_fields(rho, u).step(3)
+    got = lat.read_populations().cpu().numpy()
+    lat.close()
+    assert np.array_equal(got, fused)
+
+
+@pytest.mark.parametrize("mode", ["fused", "slabs"])
+def test_mode_switch_replaces_a_tile_the_new_mode_cannot_run(mode):
+    """An FP32 lattice 132 wide starts in pair mode with a 128 x 8 tile; one
+    node per thread that tile would need 1024 threads, so switching mode
+    picks a tile the one-node kernel can run, bit-identical to a stated one."""
+    cfg = li.params(132, 12, 10, T_over_Tc=0.8, storage="f32")
+    rho, u = li.random_fields(132, 12, 10, seed=21, rho_lo=0.15, rho_hi=0.25)
+    want = gpu_states(cfg, rho, u, [2], (32, 4, 10), "fused")[0]
+    print(f"[gpu] mode switch pairs -> {mode} on 132x12x10", flush=True)
+    lat = Lattice(cfg)
+    t0 = lat.get_tile()
+    lat.set_step_mode(mode)
+    t1 = lat.get_tile()
+    assert t0[0] * t0[1] > 512 and t1[0] * t1[1] <= 512, (t0, t1)
+    lat.init_fields(rho, u).step(2)
+    got = lat.read_populations().cpu().numpy()
+    lat.close()
+    assert np.array_equal(got, want)
+
+
 def test_split_mode_two_column_lattice():
     """FP32, nx = 2: one group per row, on the seam at both ends at once."""
     cfg = li.params(2, 6, 5, T_over_Tc=0.8, storage="f32")
@@ -380,6 +430,15 @@ def test_split_mode_rejections():
         with pytest.raises(binding.LbmError) as e:
             lat.set_tile(*tile)
         assert e.value.status == -1, tile
+    lat.close()
+    # FP32 groups of two: a 2 x 253 tile fits the groups and the LDS but its
+    # halo ring (514 nodes) exceeds the block's 512 threads.
+    lat = Lattice(li.params(6, 260, 8, storage="f32"))
+    lat.set_step_mode("split")
+    lat.set_tile(2, 252, 4)
+    with pytest.raises(binding.LbmError) as e:
+        lat.set_tile(2, 253, 4)
+    assert e.value.status == -1
     lat.close()
 
 
