@@ -11,9 +11,10 @@ STEP_TILES = {
     ("laplace_128", "f64", "fused"): (128, 4, 16),
     ("laplace_128", "f32", "fused"): (64, 4, 16),
     ("laplace_128", "f32", "pairs"): (64, 8, 8),
-    ("laplace_128", "f32", "split"): (64, 8, 16),
+    ("laplace_128", "f32", "split"): (128, 4, 16),
     ("laplace_128", "f16s", "fused"): (64, 8, 16),
     ("laplace_128", "f16s", "pairs"): (64, 8, 8),
+    ("laplace_128", "f16s", "split"): (64, 16, 8),
     ("two_droplets_256", "f64", "fused"): (128, 4, 128),
     ("two_droplets_256", "f32", "fused"): (64, 4, 128),
     ("two_droplets_256", "f32", "pairs"): (128, 8, 64),
@@ -24,15 +25,16 @@ STEP_TILES = {
     ("two_droplets_256", "f16s", "split"): (128, 8, 64),
     ("sessile_384x384x192", "f32", "fused"): (64, 4, 32),
     ("sessile_384x384x192", "f32", "pairs"): (128, 8, 16),
+    ("sessile_384x384x192", "f32", "split"): (128, 4, 48),
 }
 
 # Faster step kernel per (workload, storage); absent: "fused".
 STEP_MODES = {
     ("laplace_128", "f32"): "split",
-    ("laplace_128", "f16s"): "pairs",
+    ("laplace_128", "f16s"): "split",
     ("two_droplets_256", "f32"): "split",
     ("two_droplets_256", "f16s"): "split",
-    ("sessile_384x384x192", "f32"): "pairs",
+    ("sessile_384x384x192", "f32"): "split",
 }
 
 
