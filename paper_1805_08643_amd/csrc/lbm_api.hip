@@ -193,13 +193,19 @@ constexpr size_t kMaxStepLds = 65536;
 
 // The split kernel's LDS holds tiles of up to SPLIT_TX x SPLIT_TY nodes,
 // SPLIT_ROLE quads per role.
+// Rounds of 256 threads that a split tile's halo ring may take: the pullers'
+// and the colliders' (one for F16S groups of four, two for FP32 pairs).
+int split_rounds(int npt) { return npt == 4 ? 2 : 3; }
+
 lbm_status check_split_tile(const lbm_tile &t, int npt) {
-    // The halo ring, 2 (tx + 2) + 2 ty nodes, takes one node per thread of the block.
+    // The halo ring, 2 (tx + 2) + 2 ty nodes, takes at most split_rounds(npt)
+    // rounds of 256 threads (pullers, then colliders once for F16S, twice for FP32).
+    const int ring_max = split_rounds(npt) * SPLIT_ROLE / 2 - 2;
     if (t.tx < npt || t.ty < 1 || t.cz < 1 || t.tx % npt || t.tx > SPLIT_TX || (t.tx / npt) * t.ty > SPLIT_ROLE ||
-        t.tx * t.ty > SPLIT_NODES || (t.tx + 2) * (t.ty + 2) > SPLIT_SP || t.tx + t.ty + 2 > SPLIT_ROLE)
+        t.tx * t.ty > SPLIT_NODES || (t.tx + 2) * (t.ty + 2) > SPLIT_SP || t.tx + t.ty > ring_max)
         return fail(LBM_ERR_INVALID_ARG, "split mode needs a tile width that is a multiple of %d and at most %d, at "
                     "most %d groups of %d nodes, %d nodes, (tx + 2)(ty + 2) <= %d and tx + ty <= %d; got %d x %d x %d",
-                    npt, SPLIT_TX, SPLIT_ROLE, npt, SPLIT_NODES, SPLIT_SP, SPLIT_ROLE - 2, t.tx, t.ty, t.cz);
+                    npt, SPLIT_TX, SPLIT_ROLE, npt, SPLIT_NODES, SPLIT_SP, ring_max, t.tx, t.ty, t.cz);
     return LBM_OK;
 }
 
@@ -208,7 +214,8 @@ bool split_ring2(int tx, int ty) { return 2 * (tx + 2) + 2 * ty > SPLIT_ROLE; }
 
 // Most rows a split tile of width tx can have.
 int split_rows(int tx, int npt) {
-    return std::max(1, std::min({SPLIT_ROLE / (tx / npt), SPLIT_NODES / tx, SPLIT_SP / (tx + 2) - 2, SPLIT_ROLE - 2 - tx}));
+    return std::max(1, std::min({SPLIT_ROLE / (tx / npt), SPLIT_NODES / tx, SPLIT_SP / (tx + 2) - 2,
+                                 split_rounds(npt) * SPLIT_ROLE / 2 - 2 - tx}));
 }
 
 lbm_status check_tile(const lbm_tile &t, int storage, int npt = 1) {
@@ -289,9 +296,10 @@ bool split_apply(const lbm_params &p) {
 
 // Default tile of the split mode: rows of up to 128 nodes, up to
 // SPLIT_ROLE groups, z runs for about as many tiles as compute units.
+constexpr int SPLIT_TX_DEFAULT = 128;
 lbm_tile split_tile(int nx, int ny, int nz, int npt) {
     lbm_tile t{};
-    t.tx = std::min(SPLIT_TX, (nx + npt - 1) / npt * npt);
+    t.tx = std::min(SPLIT_TX_DEFAULT, (nx + npt - 1) / npt * npt);
     t.ty = std::max(1, std::min({ny, SPLIT_TY, split_rows(t.tx, npt)}));
     const int ncol = ((nx + t.tx - 1) / t.tx) * ((ny + t.ty - 1) / t.ty);
     const int nzc = std::max(1, (256 + ncol - 1) / ncol);
@@ -962,7 +970,7 @@ lbm_tile batch_tile(const lbm_params &p, int item_nodes, int mode) {
     lbm_tile t{};
     if (mode == LBM_STEP_SPLIT) {  // whole rows up to 128 nodes, as many rows as the LDS takes
         const int npt = npt_of(mode, p.storage);
-        t.tx = std::min(SPLIT_TX, p.nx);
+        t.tx = std::min(SPLIT_TX_DEFAULT, p.nx);
         t.ty = std::max(1, std::min(p.ny, split_rows(t.tx, npt)));
         const int cols = t.tx * t.ty;
         t.cz = std::max(1, std::min(p.nz, (item_nodes + cols / 2) / cols));

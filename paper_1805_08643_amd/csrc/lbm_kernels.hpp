@@ -1103,8 +1103,8 @@ __global__ void LBM_STEP_ATTR k_step4(const uint16_t *__restrict__ A, uint16_t *
 // populations fit in LDS.  Per-node arithmetic is that of the one-node
 // kernel: the same populations bit for bit.
 // ---------------------------------------------------------------------------
-constexpr int SPLIT_TX = 128, SPLIT_TY = 8, SPLIT_ROLE = 256;  // max tile width / rows, threads per role
-constexpr int SPLIT_SP = (SPLIT_TY + 2) * (SPLIT_TX + 2);     // psi ring slot
+constexpr int SPLIT_TX = 256, SPLIT_TY = 8, SPLIT_ROLE = 256;  // max tile width / default rows, threads per role
+constexpr int SPLIT_SP = 6 * (SPLIT_TX + 2);                    // psi ring slot: (tx + 2)(ty + 2) <= 256 x 4 + ring
 constexpr int SPLIT_NODES = 1024;                               // max nodes per tile plane
 
 struct SplitLds {
@@ -1161,23 +1161,27 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
     NbOff8<S> oin;
     oin.set(gx, wl, wr, gy, wrapi(gy - 1, ny), wrapi(gy + 1, ny), nx);
 
-    // Halo ring: nh <= 2 * SPLIT_ROLE nodes.  Each puller takes node rid and,
-    // without RING2, node rid + SPLIT_ROLE in a second round; with RING2 (a
-    // ring larger than the pullers, 20 nodes more for a 128-wide tile) the
-    // colliders take those after their collision, where they have time to
-    // spare.  Each form measured fastest where it is used, and without RING2
-    // the colliders' loop carries no halo code at all.
-    constexpr int HR = RING2 ? 1 : 2;  // halo rounds of a puller
+    // Halo ring: nh <= (1 + CR) SPLIT_ROLE nodes.  Each puller takes node rid
+    // and, without RING2 (nh <= SPLIT_ROLE), node rid + SPLIT_ROLE in a second
+    // round that is never taken.  With RING2 (a ring larger than the pullers:
+    // 20 nodes more for a 128-wide tile, 264 for a 256-wide FP32 one) the
+    // colliders take nodes rid + SPLIT_ROLE and, for FP32, rid + 2 SPLIT_ROLE
+    // after their collision, where they have time to spare.  Each form
+    // measured fastest where it is used (the colliders' second round makes
+    // FP32 1% faster and F16S 3% slower even where it is not taken), and
+    // without RING2 the colliders' loop carries no halo code at all.
+    constexpr int HR = RING2 ? 1 : 2;                // halo rounds of a puller
+    constexpr int CR = S == ST_F16S ? 1 : 2;         // halo rounds of a collider (RING2)
     const int nh = 2 * SX + 2 * TY;
     int chl[2], hxs[2], hys[2];
     bool halo[2];
     NbOff oh[2];
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-        const int h = puller ? rid + r * SPLIT_ROLE : rid + SPLIT_ROLE;
+        const int h = puller ? rid + r * SPLIT_ROLE : rid + (r + 1) * SPLIT_ROLE;
         int hlx = -1, hly = -1;
         halo[r] = false;
-        if ((puller ? r < HR : RING2 && r == 0) && h < nh) {
+        if ((puller ? r < HR : RING2 && r < CR) && h < nh) {
             if (h < SX) {
                 hlx = h - 1;
                 hly = -1;
@@ -1199,8 +1203,9 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
         oh[r].set(hxs[r], wrapi(hxs[r] - 1, nx), wrapi(hxs[r] + 1, nx), hys[r], wrapi(hys[r] - 1, ny),
                   wrapi(hys[r] + 1, ny), nx, E);
     }
-    // Colliding waves with a halo node (wave-uniform).
+    // Colliding waves with a halo node in the first / second round (wave-uniform).
     const bool chw = RING2 && !puller && (int)__builtin_amdgcn_readfirstlane(rid) + SPLIT_ROLE < nh;
+    const bool chw2 = RING2 && CR > 1 && !puller && (int)__builtin_amdgcn_readfirstlane(rid) + 2 * SPLIT_ROLE < nh;
     auto zwrap = [&](int zp) { return WALL ? zp : wrapi(zp, nz); };
     auto rslot = [&](int z) { return ring[(z - zb + 1) & 3]; };
     auto bslot = [&](int z) { return (z - zb + 3) % 3; };
@@ -1250,18 +1255,18 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
             if (active) rbuf[bs][nb + k] = rho;
         }
     };
-    // Collider's share of the halo ring of plane p (RING2).
-    auto halo_plane = [&](int p) {
+    // Collider's share of the halo ring of plane p (RING2), round r.
+    auto halo_plane = [&](int p, int r) {
         R *slot = rslot(p);
         if (WALL && (p < 0 || p >= nz)) {
             const R *gp = gpsi + (p < 0 ? 0 : (size_t)nx * ny);
-            if (halo[0]) slot[chl[0]] = gp[(size_t)hys[0] * nx + hxs[0]];
+            if (halo[r]) slot[chl[r]] = gp[(size_t)hys[r] * nx + hxs[r]];
             return;
         }
         R fh[Q];
-        pull<S, WALL>(bA, nz, PB, zwrap(p), oh[0], P, fh);
+        pull<S, WALL>(bA, nz, PB, zwrap(p), oh[r], P, fh);
         const R psh = pseudo_psi<R>(P, sum19<R>(fh));
-        if (halo[0]) slot[chl[0]] = psh;
+        if (halo[r]) slot[chl[r]] = psh;
     };
     // Collider: plane c from the LDS buffers to B.
     auto collide_plane = [&](int c) {
@@ -1311,7 +1316,10 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
             const int c = zb - 3 + i;
             if (c >= zb) collide_plane(c);
             if constexpr (RING2) {
-                if (chw && c + 2 <= ze) halo_plane(c + 2);
+                if (chw && c + 2 <= ze) halo_plane(c + 2, 0);
+                if constexpr (CR > 1) {
+                    if (chw2 && c + 2 <= ze) halo_plane(c + 2, 1);
+                }
             }
             lds_barrier();
         }

@@ -357,7 +357,9 @@ def test_split_mode_bit_identical_to_fused(storage, name, tile, op):
 SPLIT_RING_CASES = [("f16s", (132, 21, 9), (128, 8, 9), 0),  # 276-node ring, 20 on a colliding wave
                     ("f32", (132, 13, 9), (128, 4, 9), 1),   # 268, walls in z
                     ("f16s", (8, 210, 6), (4, 200, 6), 1),   # 412
-                    ("f32", (6, 260, 5), (2, 252, 5), 0)]    # 512: one node for every thread of the block
+                    ("f32", (6, 260, 5), (2, 252, 5), 0),    # 512: one node for every thread of the block
+                    ("f32", (264, 6, 5), (256, 2, 5), 0),    # 520: a second round on one colliding wave
+                    ("f32", (260, 9, 5), (256, 2, 5), 1)]    # 520, walls in z
 
 
 @pytest.mark.parametrize("storage,shape,tile,walls", SPLIT_RING_CASES)
@@ -426,19 +428,23 @@ def test_split_mode_rejections():
     lat = Lattice(li.params(32, 32, 8, storage="f16s"))
     lat.set_step_mode("split")
     lat.set_tile(32, 32, 4)  # 256 groups of four: the LDS limit
-    for tile in [(30, 4, 4), (32, 40, 4), (128, 9, 4), (256, 1, 4)]:
+    # (256, 1): F16S halo rings may take two rounds of 256 threads, not 518 nodes
+    for tile in [(30, 4, 4), (32, 40, 4), (128, 9, 4), (256, 1, 4), (260, 1, 4)]:
         with pytest.raises(binding.LbmError) as e:
             lat.set_tile(*tile)
         assert e.value.status == -1, tile
     lat.close()
-    # FP32 groups of two: a 2 x 253 tile fits the groups and the LDS but its
-    # halo ring (514 nodes) exceeds the block's 512 threads.
+    # FP32 groups of two: the tallest and the widest tiles of 256 groups are
+    # accepted (halo rings of 520 nodes, three rounds); wider, or more
+    # groups, are not.
     lat = Lattice(li.params(6, 260, 8, storage="f32"))
     lat.set_step_mode("split")
-    lat.set_tile(2, 252, 4)
-    with pytest.raises(binding.LbmError) as e:
-        lat.set_tile(2, 253, 4)
-    assert e.value.status == -1
+    lat.set_tile(2, 256, 4)
+    lat.set_tile(256, 2, 4)
+    for tile in [(258, 2, 4), (2, 257, 4), (256, 3, 4)]:
+        with pytest.raises(binding.LbmError) as e:
+            lat.set_tile(*tile)
+        assert e.value.status == -1, tile
     lat.close()
 
 
