@@ -159,6 +159,33 @@ def test_batch_full_workload_sampled_runs():
     b.close()
 
 
+def test_batch_full_workload_100_steps_split():
+    """The spot check of the 256-run workload: eight runs of every size, FP32,
+    in the split step that the tuned batch uses, against the oracle after 100
+    steps (ten 10-step graph replays), within the FP32 bound of 5e-6 per step."""
+    import os
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    runs = li.c5_batch()
+    cfgs = [dict(p, storage="f32") for p, _ in runs]
+    b = Batch(cfgs)
+    b.set_step_mode("split")
+    for k, (p, init) in enumerate(runs):
+        b.init_droplets(k, init["droplets"], init["rho_L"], init["rho_V"], init["W"])
+    b.step(100, 10)
+    threads = min(16, os.cpu_count() or 1)
+    for k in [0, 1, 7, 64, 100, 128, 200, 255]:
+        p, init = runs[k]
+        got = b.pops(k)
+        op = ref.make_params(p, nthreads=threads)
+        want = ref.step(op, ref.equilibrium(op, *li.init_fields(p, init)), 100)
+        e = float((np.abs(got - want) / want.sum(0)[None]).max())
+        print(f"  run {k} L={p['nx']}: err {e:.3e} after 100 steps", flush=True)
+        assert np.isfinite(got).all()
+        assert e < 100 * 5e-6
+    b.close()
+
+
 def test_batch_variable_viscosity_matches_single_lattices():
     """Per-run parameters travel through the batch descriptor, including the
     density-dependent viscosity."""
