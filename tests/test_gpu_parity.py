@@ -539,6 +539,51 @@ def test_mass_conservation(storage):
     assert d["status"] == 0 and d["nonfinite"] == 0
 
 
+def test_fp64_200_step_prefix_laplace_128():
+    """The 128^3 Laplace droplet in FP64, in its tuned launch configuration:
+    every population after 200 steps against the oracle, to 1e-12."""
+    import os
+    _need_gpu()
+    cfg, init = li.c2_laplace(20)
+    cfg = dict(cfg, storage="f64")
+    rho, u = li.init_fields(cfg, init)
+    mode = tuning.mode_for("laplace_128", "f64")
+    tile = tuning.tile_for("laplace_128", "f64", mode)
+    got = gpu_states(cfg, rho, u, [200], tile, mode)[0]
+    p = ref.make_params(cfg, nthreads=min(16, os.cpu_count() or 1))
+    want = ref.step(p, ref.equilibrium(p, rho, u), 200)
+    e = rho_err(got, want)
+    print(f"  200 steps: err {e:.3e}", flush=True)
+    assert e < 1e-12
+
+
+@pytest.mark.parametrize("workload,storage", [("two_droplets_256", "f64"), ("two_droplets_256", "f32"),
+                                              ("sessile_384x384x192", "f32")])
+def test_full_size_mass_over_200_steps(workload, storage):
+    """Mass is an exact invariant of the step (periodic, or half-way
+    bounce-back walls): at full size in the tuned configuration, 200 steps
+    move it by rounding only."""
+    _need_gpu()
+    cfg, init = FULL[workload]()
+    cfg = dict(cfg, storage=storage)
+    mode = tuning.mode_for(workload, storage)
+    tile = tuning.tile_for(workload, storage, mode)
+    print(f"[gpu] mass {workload} {storage} mode={mode} tile={tile}", flush=True)
+    lat = Lattice(cfg)
+    lat.set_step_mode(mode)
+    if tile:
+        lat.set_tile(*tile)
+    lat.init_droplets(init["droplets"], init["rho_L"], init["rho_V"], init["W"])
+    m0 = lat.diagnostics()["mass"]
+    lat.step(200)
+    d = lat.diagnostics()
+    lat.close()
+    rel = abs(d["mass"] - m0) / m0
+    print(f"  |dM|/M = {rel:.3e}")
+    assert d["status"] == 0 and d["nonfinite"] == 0
+    assert rel < (1e-13 if storage == "f64" else 1e-6)
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16s"])
 def test_save_load_resume_is_bit_identical(storage):
     _need_gpu()
