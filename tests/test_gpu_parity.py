@@ -170,6 +170,19 @@ def test_fp32_parity(name, op, mode):
         assert e < 5e-6 * s, (s, e)
 
 
+@pytest.mark.parametrize("mode", ["pairs", "split"])
+def test_fp32_density_500_steps_droplet_32(mode):
+    """The 32^3 droplet in FP32 storage and arithmetic: the density field after
+    500 steps within 1e-5 of the FP64 oracle, relative to the local density."""
+    cfg, rho, u, tile = _case("droplet_32", "nonorth", "f32")
+    got = gpu_states(cfg, rho, u, [500], None, mode)[0]
+    want = oracle_states(cfg, rho, u, [500])[0]
+    rg, rw = got.sum(0), want.sum(0)
+    e = float((np.abs(rg - rw) / rw).max())
+    print(f"  500 steps: density err {e:.3e}")
+    assert e < 1e-5
+
+
 @pytest.mark.parametrize("mode", ["fused", "pairs", "quads", "split"])
 @pytest.mark.parametrize("name", ["droplet_32", "ragged_70x37x21", "walls_40x33x19_60deg"])
 def test_f16s_parity(name, mode):
