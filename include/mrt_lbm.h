@@ -252,6 +252,16 @@ lbm_status lbm_set_timing(lbm_ctx *ctx, int32_t enable);
  * write pass per step, outside the timed region of lbm_set_timing; kernels
  * only, so a captured step stays capturable. */
 lbm_status lbm_set_write_check(lbm_ctx *ctx, int32_t enable);
+
+/* Cache policy of the split step's population stores (LBM_STEP_SPLIT; other
+ * step modes always store cached).  LBM_STORE_AUTO (the default) stores
+ * non-temporally when the two population arrays together exceed the GPU's
+ * 256 MiB last-level cache, where cached stores would evict the lines the next
+ * plane's reads need; LBM_STORE_CACHED and LBM_STORE_STREAM force either
+ * policy.  Results are bit for bit the same under every policy; only the
+ * speed differs.  An unknown policy returns LBM_ERR_INVALID_ARG. */
+enum { LBM_STORE_AUTO = 0, LBM_STORE_CACHED = 1, LBM_STORE_STREAM = 2 };
+lbm_status lbm_set_store_policy(lbm_ctx *ctx, int32_t policy);
 lbm_status lbm_kernel_time(lbm_ctx *ctx, double *avg_ms, int64_t *launches);
 
 int64_t lbm_step_count(const lbm_ctx *ctx);
@@ -299,6 +309,9 @@ lbm_status lbm_batch_set_blocks(lbm_batch *b, int32_t blocks);
  * LBM_STEP_PAIRS where it applies.  Rebuilds the work list and drops captured
  * graphs; results are bit for bit the same in all modes. */
 lbm_status lbm_batch_set_step_mode(lbm_batch *b, int32_t mode);
+/* Store policy of the batch's split step, as lbm_set_store_policy, judged on
+ * the whole population pool of the batch.  Drops captured graphs. */
+lbm_status lbm_batch_set_store_policy(lbm_batch *b, int32_t policy);
 lbm_status lbm_batch_get_step_mode(const lbm_batch *b, int32_t *mode);
 lbm_status lbm_batch_kernel_time(lbm_batch *b, double *avg_ms, int64_t *launches);
 int64_t lbm_batch_nodes(const lbm_batch *b);

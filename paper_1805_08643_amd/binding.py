@@ -23,6 +23,7 @@ OP = {"nonorth": 0, "orth": 1}
 STORAGE = {"f64": 0, "f32": 1, "f16s": 2}
 PSI = {"sqrt_cs": 0, "exp": 1}
 STEP_MODES = {"fused": 0, "slabs": 1, "pairs": 2, "quads": 3, "split": 4}
+STORE_POLICIES = {"auto": 0, "cached": 1, "stream": 2}
 
 
 class LbmParams(ctypes.Structure):
@@ -119,6 +120,8 @@ SIGNATURES = {
     "lbm_batch_kernel_time": (_i32, [_vp, _dp, _P(_i64)]),
     "lbm_batch_nodes": (_i64, [_vp]),
     "lbm_set_write_check": (_i32, [_vp, _i32]),
+    "lbm_set_store_policy": (_i32, [_vp, _i32]),
+    "lbm_batch_set_store_policy": (_i32, [_vp, _i32]),
     "lbm_batch_diagnostics": (_i32, [_vp, _i32, _P(LbmDiagRequest), _P(LbmDiag)]),
     "lbm_batch_status": (_i32, [_vp, _P(_i32)]),
     "lbm_batch_runs": (_i32, [_vp]),
@@ -444,6 +447,11 @@ class Lattice:
         _call("lbm_set_write_check", _vp(self.ctx), int(bool(on)))
         return self
 
+    def set_store_policy(self, policy):
+        """Split step's population stores: "auto", "cached" or "stream"."""
+        _call("lbm_set_store_policy", _vp(self.ctx), STORE_POLICIES[policy])
+        return self
+
     def get_tile(self):
         return lbm_get_tile(self.ctx)
 
@@ -561,6 +569,11 @@ class Batch:
     def set_step_mode(self, mode):
         """mode: "fused", "pairs" or "split"."""
         _call("lbm_batch_set_step_mode", _vp(self.h), STEP_MODES[mode])
+        return self
+
+    def set_store_policy(self, policy):
+        """Split step's population stores: "auto", "cached" or "stream"."""
+        _call("lbm_batch_set_store_policy", _vp(self.h), STORE_POLICIES[policy])
         return self
 
     def step_mode(self):

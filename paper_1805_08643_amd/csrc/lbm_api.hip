@@ -209,6 +209,13 @@ lbm_status check_split_tile(const lbm_tile &t, int npt) {
     return LBM_OK;
 }
 
+// Last-level cache (Infinity Cache) of the MI355X: population arrays larger
+// than this stream through it, and the split step stores them non-temporally.
+constexpr size_t kLlcBytes = 256ull << 20;
+bool stream_stores(int policy, size_t pop_bytes) {
+    return policy == LBM_STORE_STREAM || (policy == LBM_STORE_AUTO && pop_bytes > kLlcBytes);
+}
+
 // Whether a split tile's halo ring has more nodes than the pulling threads.
 bool split_ring2(int tx, int ty) { return 2 * (tx + 2) + 2 * ty > SPLIT_ROLE; }
 
@@ -328,6 +335,7 @@ struct lbm_ctx {
     int mode = LBM_STEP_FUSED;
     int slab = 32;
     bool write_check = false;
+    int store_policy = LBM_STORE_AUTO;
 
     void *state() const { return ws + (cur ? L.B : L.A); }
     void *other() const { return ws + (cur ? L.A : L.B); }
@@ -406,14 +414,16 @@ lbm_status launch_step(lbm_ctx *c, const GridDesc &g, const void *src, void *dst
                 lbm_tile t{g.tx, g.ty, g.cz, 0};
                 if (g.nx % npt) return fail(LBM_ERR_INVALID_ARG, "split mode needs nx a multiple of %d", npt);
                 if (lbm_status e = check_split_tile(t, npt)) return e;
-                if (split_ring2(g.tx, g.ty))
-                    hipLaunchKernelGGL((k_step_split<S.value, O.value, W.value, true>), dim3(grid),
-                                       dim3(2 * SPLIT_ROLE), 0, c->stream, (const T *)src, (T *)dst,
-                                       (const R *)c->gpsi(), g, c->pd);
-                else
-                    hipLaunchKernelGGL((k_step_split<S.value, O.value, W.value, false>), dim3(grid),
-                                       dim3(2 * SPLIT_ROLE), 0, c->stream, (const T *)src, (T *)dst,
-                                       (const R *)c->gpsi(), g, c->pd);
+                const bool r2 = split_ring2(g.tx, g.ty);
+                const bool nt = stream_stores(c->store_policy, 2 * (c->L.B - c->L.A));
+#define LBM_SPLIT_LAUNCH(R2, NT)                                                                              \
+    hipLaunchKernelGGL((k_step_split<S.value, O.value, W.value, R2, NT>), dim3(grid), dim3(2 * SPLIT_ROLE), 0, \
+                       c->stream, (const T *)src, (T *)dst, (const R *)c->gpsi(), g, c->pd)
+                if (r2 && nt) LBM_SPLIT_LAUNCH(true, true);
+                else if (r2) LBM_SPLIT_LAUNCH(true, false);
+                else if (nt) LBM_SPLIT_LAUNCH(false, true);
+                else LBM_SPLIT_LAUNCH(false, false);
+#undef LBM_SPLIT_LAUNCH
                 HIP_TRY(hipGetLastError());
                 return LBM_OK;
             } else {
@@ -896,6 +906,14 @@ lbm_status lbm_set_write_check(lbm_ctx *c, int32_t enable) {
     return LBM_OK;
 }
 
+lbm_status lbm_set_store_policy(lbm_ctx *c, int32_t policy) {
+    if (!c) return fail(LBM_ERR_INVALID_ARG, "ctx is NULL");
+    if (policy != LBM_STORE_AUTO && policy != LBM_STORE_CACHED && policy != LBM_STORE_STREAM)
+        return fail(LBM_ERR_INVALID_ARG, "unknown store policy %d", policy);
+    c->store_policy = policy;
+    return LBM_OK;
+}
+
 lbm_status lbm_set_timing(lbm_ctx *c, int32_t enable) {
     if (!c) return fail(LBM_ERR_INVALID_ARG, "ctx is NULL");
     c->timing = enable != 0;
@@ -954,6 +972,7 @@ struct lbm_batch {
     int item_nodes = 8192;
     int mode = LBM_STEP_FUSED;  // LBM_STEP_FUSED, LBM_STEP_PAIRS or LBM_STEP_SPLIT
     bool ring2 = false;         // split: some run's tile has a halo ring beyond the pullers
+    int store_policy = LBM_STORE_AUTO;
     long long nodes = 0;
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;
@@ -1051,21 +1070,21 @@ lbm_status batch_build(lbm_batch *b) {
 lbm_status batch_launch(lbm_batch *b, hipStream_t st, int parity, int blocks) {
     const RunDesc *d = reinterpret_cast<const RunDesc *>(b->ws + b->desc_off);
     const int nr = (int)b->runs.size();
-#define LBM_SCASE(s, o, r2)                                                                                   \
-    if (b->storage == s && b->op == o && b->mode == LBM_STEP_SPLIT && b->ring2 == r2) {                       \
-        hipLaunchKernelGGL((k_batch_split<s, o, r2>), dim3(blocks), dim3(2 * SPLIT_ROLE), 0, st, b->ws, d, nr,  \
-                           b->total_tiles, parity);                                                           \
+    const bool nt = stream_stores(b->store_policy, b->desc_off);
+#define LBM_SCASE(s, o, r2, n)                                                                                \
+    if (b->storage == s && b->op == o && b->mode == LBM_STEP_SPLIT && b->ring2 == r2 && nt == n) {            \
+        hipLaunchKernelGGL((k_batch_split<s, o, r2, n>), dim3(blocks), dim3(2 * SPLIT_ROLE), 0, st, b->ws, d,   \
+                           nr, b->total_tiles, parity);                                                       \
         HIP_TRY(hipGetLastError());                                                                           \
         return LBM_OK;                                                                                        \
     }
-    LBM_SCASE(ST_F32, OP_NONORTH, false)
-    LBM_SCASE(ST_F32, OP_ORTH, false)
-    LBM_SCASE(ST_F16S, OP_NONORTH, false)
-    LBM_SCASE(ST_F16S, OP_ORTH, false)
-    LBM_SCASE(ST_F32, OP_NONORTH, true)
-    LBM_SCASE(ST_F32, OP_ORTH, true)
-    LBM_SCASE(ST_F16S, OP_NONORTH, true)
-    LBM_SCASE(ST_F16S, OP_ORTH, true)
+#define LBM_SCASE4(s, o) LBM_SCASE(s, o, false, false) LBM_SCASE(s, o, true, false) \
+    LBM_SCASE(s, o, false, true) LBM_SCASE(s, o, true, true)
+    LBM_SCASE4(ST_F32, OP_NONORTH)
+    LBM_SCASE4(ST_F32, OP_ORTH)
+    LBM_SCASE4(ST_F16S, OP_NONORTH)
+    LBM_SCASE4(ST_F16S, OP_ORTH)
+#undef LBM_SCASE4
 #undef LBM_SCASE
 #define LBM_BCASE(s, o, pr)                                                                                   \
     if (b->storage == s && b->op == o && (b->mode == LBM_STEP_PAIRS) == pr && b->mode != LBM_STEP_SPLIT) {     \
@@ -1325,6 +1344,16 @@ lbm_status lbm_batch_set_step_mode(lbm_batch *b, int32_t mode) {
     lbm_status s = batch_build(b);
     if (s) return s;
     b->blocks = std::min(mode == LBM_STEP_SPLIT ? 256 : b->blocks, b->total_tiles);
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_set_store_policy(lbm_batch *b, int32_t policy) {
+    if (!b) return fail(LBM_ERR_INVALID_ARG, "batch is NULL");
+    if (policy != LBM_STORE_AUTO && policy != LBM_STORE_CACHED && policy != LBM_STORE_STREAM)
+        return fail(LBM_ERR_INVALID_ARG, "unknown store policy %d", policy);
+    b->store_policy = policy;
+    for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+    b->graphs.clear();
     return LBM_OK;
 }
 

@@ -144,6 +144,11 @@ constexpr int kBufWord3 = 0x00020000;  // dword 3 of a raw buffer descriptor on 
 // Cache policy of the buffer stores (same encoding).
 #define LBM_BUF_STORE_AUX LBM_BUF_AUX
 #endif
+// Non-temporal policy of the split step's streaming stores, for lattices
+// larger than the last-level cache: there the stores would only evict the
+// lines that the next plane's reads need (measured 5-6% faster at 256^3), while
+// a lattice that fits keeps its populations cached for the next step.
+#define LBM_BUF_NT 2
 __device__ inline rsrc_t make_rsrc(const void *base, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, kBufWord3);
 }

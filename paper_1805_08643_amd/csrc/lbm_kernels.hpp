@@ -1115,7 +1115,8 @@ struct SplitLds {
 
 // One tile of the split step; every thread of the 512-thread block calls it.
 // RING2: the tile's halo ring has more nodes than there are pulling threads.
-template <int S, int OP, bool WALL, bool RING2>
+// NT: the populations are stored with the non-temporal cache policy.
+template <int S, int OP, bool WALL, bool RING2, bool NT>
 __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, typename Storage<S>::T *__restrict__ B,
                                   const float *__restrict__ gpsi, const GridDesc &g, const Phys<float> &P, int tile,
                                   SplitLds &L) {
@@ -1295,7 +1296,7 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
         for (int a = 0; a < Q; ++a) {
             using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(bB.of(a), 0, 0, 0));
             __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, out.word(a)), bB.of(a), (int)oin.c,
-                                                  (int)u_so(bB, a, pz), LBM_BUF_STORE_AUX);
+                                                  (int)u_so(bB, a, pz), NT ? LBM_BUF_NT : LBM_BUF_STORE_AUX);
         }
     };
 
@@ -1326,7 +1327,7 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
     }
 }
 
-template <int S, int OP, bool WALL, bool RING2>
+template <int S, int OP, bool WALL, bool RING2, bool NT>
 __global__ void __launch_bounds__(2 * SPLIT_ROLE)
     k_step_split(const typename Storage<S>::T *__restrict__ A, typename Storage<S>::T *__restrict__ B,
                  const float *__restrict__ gpsi, GridDesc g, PhysD pd) {
@@ -1335,7 +1336,7 @@ __global__ void __launch_bounds__(2 * SPLIT_ROLE)
     if (tile >= g.ntiles) return;
     Phys<float> P;
     P.load(pd);
-    tile_split<S, OP, WALL, RING2>(A, B, gpsi, g, P, tile, lds);
+    tile_split<S, OP, WALL, RING2, NT>(A, B, gpsi, g, P, tile, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1414,7 +1415,7 @@ __global__ void LBM_STEP_ATTR
 
 // Batched runs with the split step: the same work list, one 512-thread
 // block per compute unit (the split step's LDS).
-template <int S, int OP, bool RING2>
+template <int S, int OP, bool RING2, bool NT>
 __global__ void __launch_bounds__(2 * SPLIT_ROLE)
     k_batch_split(unsigned char *__restrict__ ws, const RunDesc *__restrict__ runs, int nruns, int total_tiles,
                   int parity) {
@@ -1437,7 +1438,7 @@ __global__ void __launch_bounds__(2 * SPLIT_ROLE)
         P.load(rd.pd);
         const T *src = reinterpret_cast<const T *>(ws + (parity ? rd.offB : rd.offA));
         T *dst = reinterpret_cast<T *>(ws + (parity ? rd.offA : rd.offB));
-        tile_split<S, OP, false, RING2>(src, dst, nullptr, g, P, item - rd.tile_begin, lds);
+        tile_split<S, OP, false, RING2, NT>(src, dst, nullptr, g, P, item - rd.tile_begin, lds);
     }
 }
 

@@ -124,6 +124,26 @@ def test_batch_split_wide_run(storage):
     b.close()
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16s"])
+def test_batch_split_store_policies_bit_identical(storage):
+    """Non-temporal and cached population stores give the same bits in a
+    batch, in plain launches and graph replays."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    runs = _runs(storage, sizes=(32, 48, 20, 36))
+    out = {}
+    for policy in ("cached", "stream"):
+        b = Batch([r[0] for r in runs])
+        b.set_step_mode("split").set_store_policy(policy)
+        for k, (p, init) in enumerate(runs):
+            b.init_fields(k, *li.init_fields(p, init))
+        b.step(5, 2)
+        out[policy] = [b.pops(k) for k in range(len(runs))]
+        b.close()
+    for k in range(len(runs)):
+        assert np.array_equal(out["cached"][k], out["stream"][k]), k
+
+
 def test_batch_split_rejects_unsuitable_runs():
     """F16S split needs nx % 4 == 0 in every run."""
     if not torch.cuda.is_available():

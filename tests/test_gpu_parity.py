@@ -417,6 +417,30 @@ def test_mode_switch_replaces_a_tile_the_new_mode_cannot_run(mode):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("storage,name,tile", [("f16s", "droplet_32", (32, 8, 8)),
+                                               ("f32", "walls_40x33x19_60deg", (40, 4, 7)),
+                                               ("f32", "ragged_70x37x21", (70, 2, 21))])
+def test_split_store_policies_bit_identical(storage, name, tile):
+    """Non-temporal and cached population stores give the same bits."""
+    cfg, rho, u, _ = _case(name, "nonorth", storage)
+    out = {}
+    for policy in ("cached", "stream"):
+        print(f"[gpu] split {name} {storage} stores={policy}", flush=True)
+        lat = Lattice(cfg)
+        lat.set_step_mode("split").set_store_policy(policy)
+        lat.set_tile(*tile)
+        lat.init_fields(rho, u).step(3)
+        out[policy] = lat.read_populations().cpu().numpy()
+        lat.close()
+    assert np.array_equal(out["cached"], out["stream"])
+    lat = Lattice(cfg)
+    lat.set_store_policy("auto")
+    with pytest.raises(binding.LbmError) as e:
+        binding._call("lbm_set_store_policy", binding._vp(lat.ctx), 7)
+    assert e.value.status == -1
+    lat.close()
+
+
 def test_split_mode_two_column_lattice():
     """FP32, nx = 2: one group per row, on the seam at both ends at once."""
     cfg = li.params(2, 6, 5, T_over_Tc=0.8, storage="f32")
