@@ -223,16 +223,19 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t trials, lbm_tile *best);
  * wave into pullers (global loads, psi, populations into LDS) running three
  * planes ahead of colliders (collision from LDS, stores), so memory and
  * arithmetic overlap; F16S with nx a multiple of 4 or FP32 with even nx; tile
- * width a multiple of the group size and at most 128, at most 8 rows and 256
- * groups (128 x 8 nodes for F16S, 128 x 4 for FP32).
+ * width a multiple of the group size and at most 256, at most 256 groups and
+ * 1024 nodes, (tx + 2)(ty + 2) <= 1548, and a halo ring 2 (tx + ty) + 4 of at
+ * most 512 nodes for F16S or 768 for FP32 (tuned: 128 x 8 nodes for F16S,
+ * 128 x 4 for FP32).
  * A mode that does not apply
  * returns LBM_ERR_UNSUPPORTED.  With 2 or 4 nodes per thread the tile width
  * must be a multiple of that count (lbm_set_tile returns LBM_ERR_INVALID_ARG
- * otherwise); switching to such a mode with a tile that does not fit
- * replaces the tile by the mode's default (rows of up to 128 nodes, up to 512
- * threads).  slab_planes is used by LBM_STEP_SLABS only but must be >= 1.
+ * otherwise); switching to a mode whose kernel cannot run the current tile
+ * replaces the tile by the mode's default (rows of up to 128 nodes).
+ * slab_planes is used by LBM_STEP_SLABS only but must be >= 1.
  * All modes give the same populations bit for bit.  A new context uses
- * LBM_STEP_PAIRS where it applies and LBM_STEP_FUSED otherwise. */
+ * LBM_STEP_SPLIT where it applies, else LBM_STEP_PAIRS where that applies,
+ * else LBM_STEP_FUSED. */
 enum { LBM_STEP_FUSED = 0, LBM_STEP_SLABS = 1, LBM_STEP_PAIRS = 2, LBM_STEP_QUADS = 3, LBM_STEP_SPLIT = 4 };
 lbm_status lbm_set_step_mode(lbm_ctx *ctx, int32_t mode, int32_t slab_planes);
 /* Current step mode and slab size (slab_planes may be NULL). */
@@ -306,7 +309,8 @@ lbm_status lbm_batch_set_blocks(lbm_batch *b, int32_t blocks);
  * thread; FP32/F16S storage and even nx in every run) or LBM_STEP_SPLIT
  * (pulling and colliding waves; FP32 with even nx or F16S with nx a multiple
  * of 4 in every run); otherwise LBM_ERR_UNSUPPORTED.  A new batch uses
- * LBM_STEP_PAIRS where it applies.  Rebuilds the work list and drops captured
+ * LBM_STEP_SPLIT where it applies to every run, else LBM_STEP_PAIRS where that
+ * applies, else LBM_STEP_FUSED.  Rebuilds the work list and drops captured
  * graphs; results are bit for bit the same in all modes. */
 lbm_status lbm_batch_set_step_mode(lbm_batch *b, int32_t mode);
 /* Store policy of the batch's split step, as lbm_set_store_policy, judged on

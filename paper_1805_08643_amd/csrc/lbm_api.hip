@@ -595,7 +595,12 @@ lbm_status lbm_create(const lbm_params *p, void *dev_ws, size_t ws_bytes, void *
     c->L = L;
     c->ws = static_cast<unsigned char *>(dev_ws);
     c->stream = static_cast<hipStream_t>(hip_stream);
-    if (pairs_apply(*p)) {
+    // Default step: the split step where it applies (the fastest on every
+    // workload measured), else two nodes per thread, else one.
+    if (split_apply(*p)) {
+        c->mode = LBM_STEP_SPLIT;
+        c->tile = split_tile(p->nx, p->ny, p->nz, npt_of(LBM_STEP_SPLIT, p->storage));
+    } else if (pairs_apply(*p)) {
         c->mode = LBM_STEP_PAIRS;
         c->tile = wide_tile(p->nx, p->ny, p->nz, 2);
     } else {
@@ -1181,7 +1186,9 @@ lbm_status lbm_batch_create(const lbm_params *runs, int32_t n, void *dev_ws, siz
     b->stream = static_cast<hipStream_t>(hip_stream);
     b->op = runs[0].op;
     b->storage = runs[0].storage;
-    b->mode = batch_pairs_apply(runs, n) ? LBM_STEP_PAIRS : LBM_STEP_FUSED;
+    bool all_split = true;
+    for (int k = 0; k < n; ++k) all_split = all_split && split_apply(runs[k]);
+    b->mode = all_split ? LBM_STEP_SPLIT : batch_pairs_apply(runs, n) ? LBM_STEP_PAIRS : LBM_STEP_FUSED;
     for (int k = 0; k < n; ++k) {
         lbm_ctx *c = nullptr;
         s = lbm_create(&runs[k], b->ws + b->run_off[k], layout_of(runs[k]).total, hip_stream, &c);

@@ -42,7 +42,8 @@ def _need_gpu():
 
 def gpu_states(cfg, rho, u, checkpoints, tile=None, mode=None):
     """States after each checkpoint; mode None keeps the library's default
-    step kernel (two nodes per thread for FP32/F16S with even nx)."""
+    step kernel (the split step where it applies, else two nodes per thread,
+    else one)."""
     _need_gpu()
     print(f"[gpu] {cfg['nx']}x{cfg['ny']}x{cfg['nz']} op={cfg.get('op')} storage={cfg.get('storage')} "
           f"wall={cfg.get('wall_z', 0)} tile={tile} mode={mode} steps={checkpoints}", flush=True)
@@ -294,8 +295,9 @@ def test_pair_mode_two_column_lattice(storage):
 
 def test_default_step_mode():
     _need_gpu()
-    for shape, storage, want in [((32, 8, 8), "f32", "pairs"), ((32, 8, 8), "f16s", "pairs"),
-                                 ((32, 8, 8), "f64", "fused"), ((33, 8, 8), "f32", "fused")]:
+    for shape, storage, want in [((32, 8, 8), "f32", "split"), ((32, 8, 8), "f16s", "split"),
+                                 ((34, 8, 8), "f16s", "pairs"), ((32, 8, 8), "f64", "fused"),
+                                 ((33, 8, 8), "f32", "fused")]:
         lat = Lattice(li.params(*shape, storage=storage))
         assert lat.step_mode() == want, (shape, storage)
         lat.close()
@@ -399,14 +401,16 @@ def test_split_mode_halo_ring_beyond_pullers(storage, shape, tile, walls):
 
 @pytest.mark.parametrize("mode", ["fused", "slabs"])
 def test_mode_switch_replaces_a_tile_the_new_mode_cannot_run(mode):
-    """An FP32 lattice 132 wide starts in pair mode with a 128 x 8 tile; one
-    node per thread that tile would need 1024 threads, so switching mode
-    picks a tile the one-node kernel can run, bit-identical to a stated one."""
+    """An FP32 lattice 132 wide in pair mode with a 128 x 8 tile: one node per
+    thread that tile would need 1024 threads, so switching mode picks a tile
+    the one-node kernel can run, bit-identical to a stated one."""
     cfg = li.params(132, 12, 10, T_over_Tc=0.8, storage="f32")
     rho, u = li.random_fields(132, 12, 10, seed=21, rho_lo=0.15, rho_hi=0.25)
     want = gpu_states(cfg, rho, u, [2], (32, 4, 10), "fused")[0]
     print(f"[gpu] mode switch pairs -> {mode} on 132x12x10", flush=True)
     lat = Lattice(cfg)
+    lat.set_step_mode("pairs")
+    lat.set_tile(128, 8, 10)
     t0 = lat.get_tile()
     lat.set_step_mode(mode)
     t1 = lat.get_tile()
