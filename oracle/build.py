@@ -2,6 +2,10 @@
 
 Plain gcc, FP64, ``-ffp-contract=off`` so that no fused multiply-add changes
 the rounding of the written-out formulas, no fast-math, OpenMP over z-planes.
+
+``build(defines=..., out=...)`` also builds variant libraries for the tests
+(for example with a planted mistake, ``ORACLE_PLANT=<n>``) or with the host
+sanitizers (``sanitize=True``) into a path of the caller's choice.
 """
 from __future__ import annotations
 
@@ -13,16 +17,19 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lbm_oracle.c")
 LIB = os.path.join(HERE, "liblbm_oracle.so")
 
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-std=c11", "-Wall", "-Wextra"]
 
-def build(force: bool = True) -> str:
-    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
-        return LIB
-    tmp = LIB + ".tmp"
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-std=c11",
-           "-Wall", "-Wextra", "-shared", "-fPIC", SRC, "-o", tmp, "-lm"]
+
+def build(force: bool = True, defines: dict | None = None, out: str | None = None) -> str:
+    out = out or LIB
+    if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(SRC):
+        return out
+    tmp = out + ".tmp"
+    dflags = [f"-D{k}={v}" for k, v in (defines or {}).items()]
+    cmd = ["gcc", *CFLAGS, *dflags, "-shared", "-fPIC", SRC, "-o", tmp, "-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -34,6 +34,14 @@
 
 #define Q 19
 
+/* Planted mistakes, compiled only into the variant libraries that the tests
+ * build to show that the wetting-layer pins detect them (0 = the oracle):
+ * 1 halves phi, 2 takes layer 1 for layer 2, 3 takes phi from layer 2,
+ * 4 flips the sign of the phi term.  See compute_rho_psi. */
+#ifndef ORACLE_PLANT
+#define ORACLE_PLANT 0
+#endif
+
 /* Eq. (2), columns in order. */
 static const int EX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
 static const int EY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
@@ -214,13 +222,25 @@ static void compute_rho_psi(const oracle_params *p, const double *f, fields_t *w
         for (int side = 0; side < 2; ++side) {
             int64_t z1 = side == 0 ? 0 : nz - 1;
             int64_t z2 = side == 0 ? 1 : nz - 2;
+#if ORACLE_PLANT == 2
+            z2 = z1;
+#endif
+            int64_t zphi = z1;
+#if ORACLE_PLANT == 3
+            zphi = z2;
+#endif
             for (int64_t y = 0; y < ny; ++y)
                 for (int64_t x = 0; x < nx; ++x) {
-                    double dx = w->rho[(z1 * ny + y) * nx + wrap(x + 1, nx)] -
-                                w->rho[(z1 * ny + y) * nx + wrap(x - 1, nx)];
-                    double dy = w->rho[(z1 * ny + wrap(y + 1, ny)) * nx + x] -
-                                w->rho[(z1 * ny + wrap(y - 1, ny)) * nx + x];
+                    double dx = w->rho[(zphi * ny + y) * nx + wrap(x + 1, nx)] -
+                                w->rho[(zphi * ny + y) * nx + wrap(x - 1, nx)];
+                    double dy = w->rho[(zphi * ny + wrap(y + 1, ny)) * nx + x] -
+                                w->rho[(zphi * ny + wrap(y - 1, ny)) * nx + x];
                     double phi = sqrt(dx * dx + dy * dy);
+#if ORACLE_PLANT == 1
+                    phi *= 0.5;
+#elif ORACLE_PLANT == 4
+                    phi = -phi;
+#endif
                     double rg = w->rho[(z2 * ny + y) * nx + x] + phi * p->tan_wall;
                     if (rg < p->ghost_rho_min) rg = p->ghost_rho_min;
                     w->gpsi[side * nx * ny + y * nx + x] = oracle_psi(p, rg);

@@ -48,23 +48,28 @@ class OracleParams(ctypes.Structure):
 _lib = None
 
 
+def load(path: str):
+    """Open an oracle library (the default one, or a variant the tests
+    built) and declare its entry points."""
+    L = ctypes.CDLL(path)
+    P = ctypes.POINTER(OracleParams)
+    dp = ctypes.POINTER(ctypes.c_double)
+    i64 = ctypes.c_int64
+    L.oracle_step.argtypes = [P, dp, dp, i64]
+    L.oracle_collide_nodes.argtypes = [P, dp, i64, ctypes.POINTER(ctypes.c_int64), dp]
+    L.oracle_equilibrium.argtypes = [P, dp, dp, dp]
+    L.oracle_fields.argtypes = [P, dp, dp, dp, dp, dp, dp]
+    L.oracle_psi_array.argtypes = [P, dp, dp, i64]
+    for fn in ("oracle_step", "oracle_collide_nodes", "oracle_equilibrium",
+               "oracle_fields", "oracle_psi_array"):
+        getattr(L, fn).restype = ctypes.c_int
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
-        path = LIB if os.path.exists(LIB) else build()
-        L = ctypes.CDLL(path)
-        P = ctypes.POINTER(OracleParams)
-        dp = ctypes.POINTER(ctypes.c_double)
-        i64 = ctypes.c_int64
-        L.oracle_step.argtypes = [P, dp, dp, i64]
-        L.oracle_collide_nodes.argtypes = [P, dp, i64, ctypes.POINTER(ctypes.c_int64), dp]
-        L.oracle_equilibrium.argtypes = [P, dp, dp, dp]
-        L.oracle_fields.argtypes = [P, dp, dp, dp, dp, dp, dp]
-        L.oracle_psi_array.argtypes = [P, dp, dp, i64]
-        for fn in ("oracle_step", "oracle_collide_nodes", "oracle_equilibrium",
-                   "oracle_fields", "oracle_psi_array"):
-            getattr(L, fn).restype = ctypes.c_int
-        _lib = L
+        _lib = load(LIB if os.path.exists(LIB) else build())
     return _lib
 
 
@@ -213,12 +218,14 @@ def step_sampled(p: OracleParams, f: np.ndarray, idx) -> np.ndarray:
     return post[inv, src_dir]
 
 
-def fields(p: OracleParams, f: np.ndarray) -> dict:
+def fields(p: OracleParams, f: np.ndarray, L=None) -> dict:
+    """rho, u, total force F, psi and p of the state f (L: an oracle library
+    from ``load``; default the built one)."""
     N = nnodes(p)
     f = np.ascontiguousarray(f, dtype=np.float64).reshape(Q, N)
     rho, psi, pr = np.empty(N), np.empty(N), np.empty(N)
     u, F = np.empty((3, N)), np.empty((3, N))
-    _check(lib().oracle_fields(ctypes.byref(p), _dp(f), _dp(rho), _dp(u), _dp(F),
+    _check((L or lib()).oracle_fields(ctypes.byref(p), _dp(f), _dp(rho), _dp(u), _dp(F),
                                _dp(psi), _dp(pr)), "fields")
     return {"rho": rho, "u": u, "F": F, "psi": psi, "p": pr}
 
