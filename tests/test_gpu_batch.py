@@ -182,7 +182,8 @@ def test_batch_full_workload_sampled_runs():
 def test_batch_full_workload_100_steps_split():
     """The spot check of the 256-run workload: eight runs of every size, FP32,
     in the split step that the tuned batch uses, against the oracle after 100
-    steps (ten 10-step graph replays), within the FP32 bound of 5e-6 per step."""
+    steps (ten 10-step graph replays), within the stated FP32 bound of 1e-5
+    relative to the density."""
     import os
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -202,7 +203,7 @@ def test_batch_full_workload_100_steps_split():
         e = float((np.abs(got - want) / want.sum(0)[None]).max())
         print(f"  run {k} L={p['nx']}: err {e:.3e} after 100 steps", flush=True)
         assert np.isfinite(got).all()
-        assert e < 100 * 5e-6
+        assert e < 1e-5
     b.close()
 
 
