@@ -180,6 +180,30 @@ lbm_status lbm_init_droplets(lbm_ctx *ctx, const lbm_droplet *d, int32_t n, doub
 /* Advance nsteps time steps (asynchronous). */
 lbm_status lbm_step(lbm_ctx *ctx, int64_t nsteps);
 
+/* One time step for callers that cannot allocate memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * step of lbm_step (Sec. II, Eqs. (3)-(6), (15), (57)) from the populations
+ * in dev_src to dev_dst, with no context and no allocation of host or device
+ * memory.
+ *   p: the lattice parameters (validated as by lbm_create).
+ *   dev_src, dev_dst: distinct device buffers of 19 N storage elements each,
+ *     256-byte aligned, in the layout of the raw state (lbm_save_state):
+ *     element a * N + i holds direction a of node i, in the storage format of
+ *     p->storage; owned by the caller.  dev_src is read, dev_dst written.
+ *   hip_stream: hipStream_t (NULL = default stream), borrowed; asynchronous.
+ * It runs the step kernel and launch shape that a new context with these
+ * parameters uses, so its result is bit for bit that of lbm_step.  Scratch
+ * (the wall-plane densities and the Eq. (57) ghost psi planes, walls only)
+ * lives in a device array inside the library, LBM_NOALLOC_SCRATCH_BYTES on
+ * every GPU the library runs on, held until the process ends.  A walled
+ * lattice whose planes need more (6 nx ny values, each plane set 256-byte
+ * aligned) returns LBM_ERR_UNSUPPORTED before any HIP call.  The first call
+ * on a device looks up that device's array address (no allocation).  Calls
+ * that overlap on one GPU share its scratch and race: serialise them (one
+ * stream, or events). */
+#define LBM_NOALLOC_SCRATCH_BYTES (32 << 20)
+lbm_status lbm_step_noalloc(const lbm_params *p, const void *dev_src, void *dev_dst, void *hip_stream);
+
 /* Macroscopic fields of the current state, Eq. (6): rho (N), u (3N),
  * p = rho/3 + G psi^2/2 (N); device FP64 outputs, any may be NULL. */
 lbm_status lbm_read_fields(lbm_ctx *ctx, double *rho, double *u, double *p);

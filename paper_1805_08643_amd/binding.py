@@ -125,6 +125,7 @@ SIGNATURES = {
     "lbm_batch_diagnostics": (_i32, [_vp, _i32, _P(LbmDiagRequest), _P(LbmDiag)]),
     "lbm_batch_status": (_i32, [_vp, _P(_i32)]),
     "lbm_batch_runs": (_i32, [_vp]),
+    "lbm_step_noalloc": (_i32, [_P(LbmParams), _vp, _vp, _vp]),
 }
 
 _lib = None
@@ -191,6 +192,10 @@ def lbm_init_droplets(ctx, droplets, rho_L, rho_V, W):
 
 def lbm_step(ctx, nsteps):
     _call("lbm_step", _vp(ctx), nsteps)
+
+
+def lbm_step_noalloc(p: LbmParams, src_ptr: int, dst_ptr: int, stream: int):
+    _call("lbm_step_noalloc", ctypes.byref(p), _vp(src_ptr), _vp(dst_ptr), _vp(stream))
 
 
 def lbm_read_fields(ctx, rho_ptr, u_ptr, p_ptr):

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -17,6 +18,12 @@
 #include "lbm_kernels.hpp"
 
 using namespace lbm;
+
+// Scratch of the allocation-free step (lbm_step_noalloc): one copy per GPU,
+// resident from the library's load until the process ends.  In host code the
+// name is only a stand-in for the symbol: its device address comes from
+// hipGetSymbolAddress (scratch_of_current_device below).
+static __device__ __align__(256) unsigned char scratch[LBM_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -337,11 +344,15 @@ struct lbm_ctx {
     bool write_check = false;
     int store_policy = LBM_STORE_AUTO;
 
+    // Wall-plane densities and ghost psi (Eq. (57)) in a buffer of their own
+    // instead of the workspace: the allocation-free step (lbm_step_noalloc).
+    unsigned char *wall_scratch = nullptr;
+
     void *state() const { return ws + (cur ? L.B : L.A); }
     void *other() const { return ws + (cur ? L.A : L.B); }
     void *psi() const { return ws + L.psi; }
-    void *rho_w() const { return ws + L.rho_w; }
-    void *gpsi() const { return ws + L.gpsi; }
+    void *rho_w() const { return wall_scratch ? wall_scratch : ws + L.rho_w; }
+    void *gpsi() const { return wall_scratch ? wall_scratch + (L.gpsi - L.rho_w) : ws + L.gpsi; }
     double *partial() const { return reinterpret_cast<double *>(ws + L.partial); }
     double *dout() const { return reinterpret_cast<double *>(ws + L.dout); }
 };
@@ -530,6 +541,45 @@ lbm_status one_step(lbm_ctx *c) {
     return LBM_OK;
 }
 
+// Default step of a new context: the split step where it applies (the
+// fastest on every workload measured), else two nodes per thread, else one.
+void default_mode(lbm_ctx *c) {
+    const lbm_params &p = c->p;
+    if (split_apply(p)) {
+        c->mode = LBM_STEP_SPLIT;
+        c->tile = split_tile(p.nx, p.ny, p.nz, npt_of(LBM_STEP_SPLIT, p.storage));
+    } else if (pairs_apply(p)) {
+        c->mode = LBM_STEP_PAIRS;
+        c->tile = wide_tile(p.nx, p.ny, p.nz, 2);
+    } else {
+        c->mode = LBM_STEP_FUSED;
+        c->tile = default_tile(p.nx, p.ny, p.nz);
+    }
+    fill_grid(c->g, p, c->tile);
+}
+
+// Device address of the allocation-free step's scratch array on the current
+// device: looked up once per device with hipGetSymbolAddress (with that device
+// current) and kept; host code passes only this pointer to kernels.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+lbm_status scratch_of_current_device(unsigned char **out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LBM_ERR_UNSUPPORTED, "device index %d >= %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(LBM_ERR_HIP, "no device address for the scratch array on device %d", dev);
+        g_scratch_ptr[dev] = static_cast<unsigned char *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return LBM_OK;
+}
+
 lbm_status compute_psi_full(lbm_ctx *c) {
     lbm_status s = launch_walls(c, c->state());
     if (s) return s;
@@ -595,18 +645,7 @@ lbm_status lbm_create(const lbm_params *p, void *dev_ws, size_t ws_bytes, void *
     c->L = L;
     c->ws = static_cast<unsigned char *>(dev_ws);
     c->stream = static_cast<hipStream_t>(hip_stream);
-    // Default step: the split step where it applies (the fastest on every
-    // workload measured), else two nodes per thread, else one.
-    if (split_apply(*p)) {
-        c->mode = LBM_STEP_SPLIT;
-        c->tile = split_tile(p->nx, p->ny, p->nz, npt_of(LBM_STEP_SPLIT, p->storage));
-    } else if (pairs_apply(*p)) {
-        c->mode = LBM_STEP_PAIRS;
-        c->tile = wide_tile(p->nx, p->ny, p->nz, 2);
-    } else {
-        c->tile = default_tile(p->nx, p->ny, p->nz);
-    }
-    fill_grid(c->g, *p, c->tile);
+    default_mode(c);
     *out = c;
     return LBM_OK;
 }
@@ -666,6 +705,32 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
         if (s) return s;
     }
     return LBM_OK;
+}
+
+lbm_status lbm_step_noalloc(const lbm_params *p, const void *dev_src, void *dev_dst, void *hip_stream) {
+    lbm_status s = validate(p);
+    if (s) return s;
+    if (!dev_src || !dev_dst) return fail(LBM_ERR_INVALID_ARG, "population buffer is NULL");
+    if (dev_src == dev_dst) return fail(LBM_ERR_INVALID_ARG, "source and destination must differ");
+    if (reinterpret_cast<uintptr_t>(dev_src) % kAlign || reinterpret_cast<uintptr_t>(dev_dst) % kAlign)
+        return fail(LBM_ERR_INVALID_ARG, "population buffers must be %zu-byte aligned", kAlign);
+    // Scratch: the wall-plane densities and the ghost psi planes (walls only).
+    const Layout L = layout_of(*p);
+    const size_t need = p->wall_z ? L.partial - L.rho_w : 0;
+    if (need > (size_t)LBM_NOALLOC_SCRATCH_BYTES)
+        return fail(LBM_ERR_UNSUPPORTED, "walled lattice %d x %d needs %zu bytes of scratch, more than the %d of "
+                    "lbm_step_noalloc", p->nx, p->ny, need, LBM_NOALLOC_SCRATCH_BYTES);
+    unsigned char *scr = nullptr;
+    if ((s = scratch_of_current_device(&scr))) return s;
+    lbm_ctx c;  // on the stack: no host allocation
+    c.p = *p;
+    c.pd = make_phys(*p);
+    c.L = L;
+    c.stream = static_cast<hipStream_t>(hip_stream);
+    c.wall_scratch = scr;
+    default_mode(&c);
+    if ((s = launch_walls(&c, dev_src))) return s;
+    return launch_step(&c, c.g, dev_src, dev_dst, npt_of(c.mode, p->storage));
 }
 
 lbm_status lbm_read_fields(lbm_ctx *c, double *rho, double *u, double *p) {
