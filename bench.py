@@ -23,6 +23,11 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS + % of HBM roofline; FP32/FP16-storage vs FP64 at stated error"
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 WORKLOAD = "two_droplets_256"
+WORKLOADS = {
+    "two_droplets_256": "256^3 periodic, two droplets r0=30 approaching at 0.05, C-S T=0.6Tc a=0.25, sigma=0.105",
+    "sessile_384x384x192": "384x384x192, periodic x and y, half-way bounce-back walls in z with the Eq. (57) "
+                           "wetting layer at 60 deg, sessile droplet r0=40, C-S T=0.7Tc, gravity 1e-6",
+}
 
 
 def parse():
@@ -32,37 +37,55 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16s", "f64"])
     ap.add_argument("--op", default="nonorth", choices=["nonorth", "orth"])
+    ap.add_argument("--workload", default=WORKLOAD, choices=sorted(WORKLOADS) + ["batch_256"],
+                    help="lattice to time (default: the 256^3 two-droplet workload); batch_256 times only the "
+                         "256-run batch")
     ap.add_argument("--mode", default=None, choices=["fused", "pairs", "quads", "split"],
                     help="step kernel; default: the faster one measured for the storage")
+    ap.add_argument("--tile", default=None, help="launch shape tx,ty,cz instead of the tuned one")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cpu-workloads", action="store_true",
                     help="only time the oracle on the host for every standard workload (one JSON line each)")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="only run a plain 1 GiB device copy 5 times (HBM counter calibration)")
+                    help="only run the hand-written 1 GiB device copy 5 times (HBM counter calibration)")
+    ap.add_argument("--ceiling-probe", action="store_true",
+                    help="only run the data-movement probes (flat copy, 19-plane streaming, tile march) at the "
+                         "byte volume of the FP32 256^3 step and print their rates")
     return ap.parse_args()
 
 
-def copy_probe(reps=5, quiet=False):
-    """A plain device-to-device copy of known size: 1 GiB read + 1 GiB written
-    per launch, used to scale the HBM byte counters of rocprofv3 and as the
-    practical read+write rate of the part."""
+def _timed(launch, reps):
+    """Mean ms of `launch` over reps launches, HIP events on torch's current
+    stream (the stream the probes are launched on)."""
     import torch
-    n = 1 << 28  # float32 elements = 1 GiB
-    src = torch.ones(n, dtype=torch.float32, device="cuda")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
+    launch()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        dst.copy_(src)
+        launch()
     e1.record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    out = {"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
-           "ms_per_copy": round(ms, 4), "GBps_read_plus_write": round(8 * n / (ms * 1e-3) / 1e9, 1)}
+    return e0.elapsed_time(e1) / reps
+
+
+def copy_probe(reps=5, quiet=False, nbytes=1 << 30, streaming=True, blocks=32768):
+    """A hand-written device copy of known size (16-byte accesses, 32768
+    blocks of 256 threads, streaming stores): 1 GiB read + 1 GiB written per
+    launch, used to scale the HBM byte counters of rocprofv3 and as the
+    practical read+write rate of the part."""
+    import torch
+
+    from paper_1805_08643_amd import probe
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    st = torch.cuda.current_stream().cuda_stream
+    ms = _timed(lambda: probe.lbm_probe_copy(src.data_ptr(), dst.data_ptr(), nbytes, streaming, blocks, st), reps)
+    out = {"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "streaming_stores": streaming,
+           "ms_per_copy": round(ms, 4), "GBps_read_plus_write": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+    assert torch.equal(src[:1024], dst[:1024])
     del src, dst
     torch.cuda.empty_cache()
     if not quiet:
@@ -70,16 +93,68 @@ def copy_probe(reps=5, quiet=False):
     return out
 
 
-def make_lattice(storage, op, mode=None):
+def ceiling_probe(reps=10, quick=False):
+    """Rates of pure data movement at the byte volume of one FP32 step of the
+    256^3 lattice (19 planes of 256^3 values, 1.27 GB read and 1.27 GB
+    written), in the access patterns of the step kernels.  quick: only the
+    fastest flat copy and 19-plane stream (streaming stores)."""
+    import torch
+
+    from paper_1805_08643_amd import probe
+    n, s = 256, 4
+    plane_bytes = n ** 3 * s
+    total = 19 * plane_bytes
+    src = torch.ones(total // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    st = torch.cuda.current_stream().cuda_stream
+    rows = []
+
+    def rec(kind, ms, **kw):
+        rows.append({"probe": kind, **kw, "ms": round(ms, 4),
+                     "GBps_read_plus_write": round(2 * total / (ms * 1e-3) / 1e9, 1),
+                     "frac_of_8TBps": round(2 * total / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)})
+
+    if quick:
+        ms = _timed(lambda: probe.lbm_probe_copy(src.data_ptr(), dst.data_ptr(), total, 1, 32768, st), reps)
+        rec("flat_copy_16B", ms, streaming_stores=1, blocks=32768)
+        ms = _timed(lambda: probe.lbm_probe_stream19(src.data_ptr(), dst.data_ptr(), plane_bytes, 8, 1, 0, st), reps)
+        rec("stream19", ms, group_bytes=8, streaming_stores=1, blocks=8192)
+    for nt in (() if quick else (0, 1)):
+        for blocks in (2048, 8192, 32768):
+            ms = _timed(lambda: probe.lbm_probe_copy(src.data_ptr(), dst.data_ptr(), total, nt, blocks, st), reps)
+            rec("flat_copy_16B", ms, streaming_stores=nt, blocks=blocks)
+        for gb in (8, 16):
+            ms = _timed(lambda: probe.lbm_probe_stream19(src.data_ptr(), dst.data_ptr(), plane_bytes, gb, nt, 0, st),
+                        reps)
+            rec("stream19", ms, group_bytes=gb, streaming_stores=nt, blocks=8192)
+        # the split step's FP32 tiles: 128 x 4 nodes (64 x 4 groups of two), z runs of 128 planes
+        for gb, tx, ty, cz in ((8, 64, 4, 128), (16, 32, 4, 128), (8, 64, 8, 64), (8, 128, 2, 128)):
+            nodes_per_group = gb // s
+            ms = _timed(lambda: probe.lbm_probe_march19(src.data_ptr(), dst.data_ptr(), n // nodes_per_group, n, n,
+                                                        gb, tx, ty, cz, nt, st), reps)
+            rec("march19", ms, group_bytes=gb, tile_groups=[tx, ty, cz], tile_nodes=[tx * nodes_per_group, ty, cz],
+                streaming_stores=nt)
+    assert torch.equal(src[-1024:], dst[-1024:])
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes_read": total, "bytes_written": total, "rows": rows,
+            "best_GBps": max(r["GBps_read_plus_write"] for r in rows)}
+
+
+def make_lattice(storage, op, mode=None, workload=WORKLOAD, tile=None):
     import lbm_inputs as li
     from paper_1805_08643_amd import tuning
     from paper_1805_08643_amd.binding import Lattice, f16_exp_for
-    cfg, init = li.c3_two_droplets(op=op)
+    if workload == "sessile_384x384x192":
+        cfg, init = li.c4_sessile(60.0)
+        cfg = dict(cfg, op=op)
+    else:
+        cfg, init = li.c3_two_droplets(op=op)
     cfg = dict(cfg, storage=storage, rho_ref=init["rho_V"], f16_exp=f16_exp_for(1.25 * init["rho_L"]))
     lat = Lattice(cfg, "cuda:0")
-    mode = mode or tuning.mode_for(WORKLOAD, storage)
+    mode = mode or tuning.mode_for(workload, storage)
     lat.set_step_mode(mode)
-    tile = tuning.tile_for(WORKLOAD, storage, mode)
+    tile = tile or tuning.tile_for(workload, storage, mode)
     if tile:
         lat.set_tile(*tile)
     lat.mode = mode
@@ -198,12 +273,12 @@ KERNEL_NAMES = {"fused": "k_step (fused psi/force + collide + pull-stream)",
                          "colliding waves)"}
 
 
-def read_traffic(storage, op, mode):
+def read_traffic(storage, op, mode, workload=WORKLOAD):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it covers this kernel built from the current sources; None otherwise."""
     from paper_1805_08643_amd.build import source_digest
     kern = {"pairs": "step2", "quads": "step4", "split": "step_split"}.get(mode, "step")
-    path = os.path.join(ROOT, "profiles", f"{kern}_{WORKLOAD}_{storage}_{op}_pmc.md")
+    path = os.path.join(ROOT, "profiles", f"{kern}_{workload}_{storage}_{op}_pmc.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -247,7 +322,8 @@ def cpu_baseline(cfg, init, budget_s):
     return {"value": N * steps / sec / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": f"full {cfg['nx']}x{cfg['ny']}x{cfg['nz']} lattice, FP64 dense-matrix oracle, "
                       f"{steps} step(s) after 1 untimed step",
-            "single_thread_mlups": round(st1, 3), "single_thread_sample": "64^3 droplet, 2 steps, 1 thread"}
+            "single_thread_mlups": round(st1, 3), "single_thread_sample": "64^3 droplet, 2 steps, 1 thread",
+            "host_cpu": host_cpu(), "logical_cpus": os.cpu_count()}
 
 
 def host_cpu():
@@ -317,9 +393,18 @@ def main():
     if a.copy_probe:
         copy_probe()
         return
+    if a.ceiling_probe:
+        print(json.dumps(ceiling_probe()), flush=True)
+        return
     from paper_1805_08643_amd.binding import algorithmic_bytes_per_node
 
-    lat, cfg, init = make_lattice(a.storage, a.op, a.mode)
+    if a.workload == "batch_256":
+        out = {"workload": "batch_256: 256 periodic droplet runs, L ~ U{32, 48, 64, 96}, seed 1805",
+               "batch": bench_batch(a.storage, steps=a.steps // 4 or 10)}
+        print(json.dumps(out), flush=True)
+        return
+    tile = tuple(int(v) for v in a.tile.split(",")) if a.tile else None
+    lat, cfg, init = make_lattice(a.storage, a.op, a.mode, a.workload, tile)
     mode = lat.mode
     N = cfg["nx"] * cfg["ny"] * cfg["nz"]
     ms, wall, kms = time_steps(lat, a.steps, a.warmup, kernel_timing=True)
@@ -332,14 +417,13 @@ def main():
     mlups = N / (ms_step * 1e-3) / 1e6
     bpn = algorithmic_bytes_per_node(a.storage)
     achieved = bpn * N / (kms * 1e-3) / 1e9
-    traffic = read_traffic(a.storage, a.op, mode)
+    traffic = read_traffic(a.storage, a.op, mode, a.workload)
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if a.storage == "f64" else "f32", "data": "synthetic",
-        "config": {"workload": f"{WORKLOAD}: 256^3 periodic, two droplets r0=30 approaching at 0.05, "
-                               f"C-S T=0.6Tc a=0.25, sigma=0.105",
+        "config": {"workload": f"{a.workload}: {WORKLOADS[a.workload]}",
                    "storage": a.storage, "op": a.op, "nodes": N, "tile": list(tile), "step_mode": mode},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
@@ -347,7 +431,7 @@ def main():
                      "kernel_ms": round(kms, 5), "algorithmic_bytes_per_node": bpn},
         "mass": diag["mass"], "nonfinite": diag["nonfinite"],
     }
-    if not a.no_variants:
+    if not a.no_variants and a.workload == WORKLOAD:
         var = {}
         for st, op, md in [("f32", "nonorth", "fused"), ("f32", "nonorth", "pairs"), ("f32", "nonorth", "split"),
                            ("f16s", "nonorth", "fused"),
@@ -367,10 +451,14 @@ def main():
             torch.cuda.empty_cache()
         out["variants_mlups"] = var
         out["batch"] = {st: bench_batch(st) for st in ("f32", "f16s")}
-    cp = copy_probe(reps=10, quiet=True)
-    out["roofline"]["copy_probe_GBps"] = cp["GBps_read_plus_write"]
-    out["roofline"]["frac_of_copy_probe"] = round(achieved / cp["GBps_read_plus_write"], 4)
-    if not a.no_cpu:
+    cp = ceiling_probe(reps=10, quick=True)["rows"]
+    out["roofline"]["copy_probe_GBps"] = cp[0]["GBps_read_plus_write"]
+    out["roofline"]["stream19_probe_GBps"] = cp[1]["GBps_read_plus_write"]
+    out["roofline"]["probes"] = ("hand-written device copy and 19-plane stream of the FP32 256^3 step's bytes "
+                                 "(2.55 GB read + written), streaming stores")
+    out["roofline"]["frac_of_copy_probe"] = round(achieved / cp[0]["GBps_read_plus_write"], 4)
+    out["roofline"]["frac_of_stream19_probe"] = round(achieved / cp[1]["GBps_read_plus_write"], 4)
+    if not a.no_cpu and a.workload == WORKLOAD:
         out["cpu_baseline"] = cpu_baseline(cfg, init, a.cpu_seconds)
     print(json.dumps(out), flush=True)
 

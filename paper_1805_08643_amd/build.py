@@ -17,6 +17,11 @@ DEPS = [SRC, os.path.join(HERE, "csrc", "lbm_kernels.hpp"), os.path.join(HERE, "
         os.path.join(ROOT, "include", "mrt_lbm.h")]
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libmrtlbm.so")
+# Data-movement probes of the HBM ceiling (include/mrt_probe.h), a library of
+# their own so that the step library carries none of them.
+PROBE_SRC = os.path.join(HERE, "csrc", "probe.hip")
+PROBE_DEPS = [PROBE_SRC, os.path.join(ROOT, "include", "mrt_probe.h"), os.path.join(ROOT, "include", "mrt_lbm.h")]
+PROBE_LIB = os.path.join(LIBDIR, "libmrtprobe.so")
 ARCH = "gfx950"
 
 
@@ -45,17 +50,26 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def build(force: bool = True, extra=(), out: str | None = None) -> str:
-    out = out or LIB
-    if not force and os.path.exists(out) and all(os.path.getmtime(out) >= os.path.getmtime(d) for d in DEPS):
+def _compile(src, deps, out, force, extra=()):
+    if not force and os.path.exists(out) and all(os.path.getmtime(out) >= os.path.getmtime(d) for d in deps):
         return out
     os.makedirs(os.path.dirname(out), exist_ok=True)
     tmp = out + ".tmp"
-    cmd = [hipcc(), *flags(extra), SRC, "-o", tmp]
+    cmd = [hipcc(), *flags(extra), src, "-o", tmp]
     subprocess.run(cmd, check=True)
     os.replace(tmp, out)
     return out
 
 
+def build(force: bool = True, extra=(), out: str | None = None) -> str:
+    return _compile(SRC, DEPS, out or LIB, force, extra)
+
+
+def build_probe(force: bool = True) -> str:
+    return _compile(PROBE_SRC, PROBE_DEPS, PROBE_LIB, force)
+
+
 if __name__ == "__main__":
-    print(build(force="--if-stale" not in sys.argv))
+    force = "--if-stale" not in sys.argv
+    print(build(force=force))
+    print(build_probe(force=force))

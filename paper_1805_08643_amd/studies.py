@@ -558,7 +558,9 @@ def laplace_cs(ops=("nonorth", "orth"), storages=("f64", "f32"), radii=(24, 28, 
 def precision(steps=(100, 500, 1000, 2000), n=256, crop=64):
     """Density error of FP32 and shifted-FP16 storage against FP64 storage on
     the central crop^3 box, the droplet-pair observables, and the relative
-    mass drift of each run."""
+    mass drift of each run.  Shifted FP16 runs with the default shift
+    rho_ref = rho_V ("f16s") and the two control shifts, rho_ref = 0
+    ("f16s_rho0", unshifted) and rho_ref = (rho_L + rho_V) / 2 ("f16s_mid")."""
     import torch
 
     import lbm_inputs as li
@@ -566,9 +568,12 @@ def precision(steps=(100, 500, 1000, 2000), n=256, crop=64):
     if isinstance(steps, int):
         steps = (steps,)
     cfg, init = li.c3_two_droplets(n=n)
+    shifts = {"f16s": init["rho_V"], "f16s_rho0": 0.0, "f16s_mid": 0.5 * (init["rho_L"] + init["rho_V"])}
+    variants = ("f32", "f16s", "f16s_rho0", "f16s_mid")
     lats = {}
-    for st in ("f64", "f32", "f16s"):
-        c = dict(cfg, storage=st, rho_ref=init["rho_V"], f16_exp=f16_exp_for(1.25 * init["rho_L"]))
+    for st in ("f64",) + variants:
+        c = dict(cfg, storage="f16s" if st.startswith("f16s") else st, rho_ref=shifts.get(st, init["rho_V"]),
+                 f16_exp=f16_exp_for(1.25 * init["rho_L"]))
         lat = _lattice(c)
         lat.init_droplets(init["droplets"], init["rho_L"], init["rho_V"], init["W"])
         lats[st] = lat
@@ -590,8 +595,8 @@ def precision(steps=(100, 500, 1000, 2000), n=256, crop=64):
         done = s
         ref = fields["f64"]
         liquid = ref > 0.5 * (init["rho_L"] + init["rho_V"])
-        row = dict(study="precision", step=s, f64=obs["f64"])
-        for st in ("f32", "f16s"):
+        row = dict(study="precision", step=s, f64=obs["f64"], rho_ref=shifts)
+        for st in variants:
             rel = (fields[st] - ref).abs() / ref
             row[st] = dict(rho_max_rel_err_liquid=float(rel[liquid].max()) if bool(liquid.any()) else None,
                            rho_max_rel_err_vapour=float(rel[~liquid].max()),

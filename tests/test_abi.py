@@ -11,8 +11,8 @@ from paper_1805_08643_amd import binding
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def header_functions():
-    txt = open(os.path.join(ROOT, "include", "mrt_lbm.h")).read()
+def header_functions(header="mrt_lbm.h"):
+    txt = open(os.path.join(ROOT, "include", header)).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", txt)))
 
@@ -24,6 +24,33 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
     assert sorted(binding.SIGNATURES) == names
+
+
+def test_probe_library_exports_every_declared_symbol():
+    from paper_1805_08643_amd import probe
+    L = probe.lib()
+    names = header_functions("mrt_probe.h")
+    assert names == sorted(probe.SIGNATURES)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_every_header_is_covered():
+    assert sorted(os.listdir(os.path.join(ROOT, "include"))) == ["mrt_lbm.h", "mrt_probe.h"]
+
+
+def test_probe_rejects_bad_arguments_before_any_launch():
+    from paper_1805_08643_amd import probe
+    with pytest.raises(binding.LbmError):
+        probe.lbm_probe_copy(256, 256, 1024, 0, 0, 0)  # same buffer
+    with pytest.raises(binding.LbmError):
+        probe.lbm_probe_copy(256, 512, 1000, 0, 0, 0)  # not a multiple of 16
+    with pytest.raises(binding.LbmError):
+        probe.lbm_probe_stream19(256, 512, 1024, 12, 0, 0, 0)  # group size
+    with pytest.raises(binding.LbmError):
+        probe.lbm_probe_march19(256, 512, 8, 8, 8, 8, 64, 32, 8, 0, 0)  # tx * ty > 1024
+    with pytest.raises(binding.LbmError):
+        probe.lbm_probe_march19(264, 512, 8, 8, 8, 8, 8, 8, 8, 0, 0)  # misaligned
 
 
 def test_params_default_and_workspace_size():
