@@ -111,6 +111,14 @@ typedef struct lbm_params {
     int32_t wall_x, wall_y;
     double lid_u[3];
     double lid_rho;
+    /* Failure detection (the instability of Sec. IV.A at too small a
+     * viscosity): with diag_every = K > 0, lbm_step checks the populations
+     * for NaN / Inf every time the step count reaches a multiple of K (one
+     * reduction on the device and one synchronisation of the stream) and
+     * returns LBM_ERR_NONFINITE at the first check that finds any, the state
+     * left at that step.  0: no checks.  Must be >= 0. */
+    int32_t diag_every;
+    int32_t reserved0;
 } lbm_params;
 
 /* Launch shape of the fused step: tx * ty threads per block, one thread per
@@ -177,8 +185,23 @@ lbm_status lbm_init_fields(lbm_ctx *ctx, const double *rho, const double *u);
 lbm_status lbm_init_droplets(lbm_ctx *ctx, const lbm_droplet *d, int32_t n, double rho_L,
                              double rho_V, double W);
 
-/* Advance nsteps time steps (asynchronous). */
+/* Advance nsteps time steps (asynchronous unless diag_every > 0): each step is
+ * the update of Sec. II -- density and pseudopotential (Eq. (6), Eq. (58)),
+ * interaction force (Eq. (15), Eq. (57) at walls), velocity (Eq. (6)),
+ * collision in moment space (Eqs. (4), (11)-(14), (16)) and pull streaming
+ * with periodic wrap or half-way bounce-back (Eq. (5)).  With graph steps set
+ * (lbm_set_graph_steps), runs of that many steps replay a captured hipGraph. */
 lbm_status lbm_step(lbm_ctx *ctx, int64_t nsteps);
+
+/* Replay steps from captured hipGraphs of k steps each (k >= 1), or plain
+ * launches (k = 0, the default): lbm_step then launches one graph per k steps
+ * (captured on first use on a stream of the library, one graph per buffer
+ * parity) and the rest step by step.  Bit for bit the same results; it cuts
+ * the launch cost of small lattices.  Changing the tile, the step mode, the
+ * store policy or the write check drops the captured graphs.  Steps are not
+ * replayed from graphs while kernel timing (lbm_set_timing) is on.
+ * k < 0: LBM_ERR_INVALID_ARG. */
+lbm_status lbm_set_graph_steps(lbm_ctx *ctx, int32_t k);
 
 /* One time step for callers that cannot allocate memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
@@ -215,9 +238,12 @@ lbm_status lbm_read_fields(lbm_ctx *ctx, double *rho, double *u, double *p);
 lbm_status lbm_read_populations(lbm_ctx *ctx, double *f);
 lbm_status lbm_write_populations(lbm_ctx *ctx, const double *f);
 
-/* FP64 global sums (see lbm_diag).  req may be NULL (no Laplace sums).
- * out: host pointer.  Synchronises the stream.  Returns LBM_ERR_NONFINITE
- * (with out filled) when any population is not finite. */
+/* FP64 global sums of the current state (see lbm_diag): mass and momentum
+ * (Eq. (6), with F/2), max |u|, and the sums of p = rho/3 + G psi^2 / 2 and
+ * rho inside and outside a sphere for the Laplace law (Sec. IV.B); fixed
+ * summation order, so the same state gives the same bits.  req may be NULL
+ * (no Laplace sums).  out: host pointer.  Synchronises the stream.  Returns
+ * LBM_ERR_NONFINITE (with out filled) when any population is not finite. */
 lbm_status lbm_diagnostics(lbm_ctx *ctx, const lbm_diag_request *req, lbm_diag *out);
 
 /* Raw state (storage-format populations plus the step counter) to/from a

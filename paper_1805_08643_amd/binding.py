@@ -42,6 +42,7 @@ class LbmParams(ctypes.Structure):
         ("nu_ratio", ctypes.c_double), ("visc_rho_L", ctypes.c_double), ("visc_rho_V", ctypes.c_double),
         ("wall_x", ctypes.c_int32), ("wall_y", ctypes.c_int32),
         ("lid_u", ctypes.c_double * 3), ("lid_rho", ctypes.c_double),
+        ("diag_every", ctypes.c_int32), ("reserved0", ctypes.c_int32),
     ]
 
 
@@ -126,6 +127,7 @@ SIGNATURES = {
     "lbm_batch_status": (_i32, [_vp, _P(_i32)]),
     "lbm_batch_runs": (_i32, [_vp]),
     "lbm_step_noalloc": (_i32, [_P(LbmParams), _vp, _vp, _vp]),
+    "lbm_set_graph_steps": (_i32, [_vp, _i32]),
 }
 
 _lib = None
@@ -352,6 +354,7 @@ def make_params(cfg: dict) -> LbmParams:
     for d in range(3):
         p.lid_u[d] = lu[d]
     p.lid_rho = cfg.get("lid_rho", 1.0)
+    p.diag_every = int(cfg.get("diag_every", 0))
     return p
 
 
@@ -474,6 +477,11 @@ class Lattice:
 
     def set_timing(self, on=True):
         lbm_set_timing(self.ctx, on)
+
+    def set_graph_steps(self, k):
+        """Replay runs of k steps from captured hipGraphs (0: plain launches)."""
+        _call("lbm_set_graph_steps", _vp(self.ctx), int(k))
+        return self
 
     def kernel_time(self):
         return lbm_kernel_time(self.ctx)
@@ -615,7 +623,3 @@ def storage_bytes(storage: str) -> int:
 def algorithmic_bytes_per_node(storage: str) -> int:
     """19 population reads + 19 writes per lattice update."""
     return 38 * storage_bytes(storage)
-
-
-def tan_wall(theta_deg: float) -> float:
-    return math.tan(math.radians(90.0 - theta_deg))

@@ -104,6 +104,7 @@ lbm_status validate(const lbm_params *p) {
                     p->visc_rho_V, p->visc_rho_L);
     for (int d = 0; d < 3; ++d)
         if (!std::isfinite(p->gravity[d])) return fail(LBM_ERR_INVALID_ARG, "gravity not finite");
+    if (p->diag_every < 0) return fail(LBM_ERR_INVALID_ARG, "diag_every must be >= 0");
     if (!(p->theta_wall_deg > 0.0 && p->theta_wall_deg < 180.0))
         return fail(LBM_ERR_INVALID_ARG, "theta_wall_deg must be in (0, 180)");
     if (!std::isfinite(p->rho_ref) || !std::isfinite(p->ghost_rho_min))
@@ -343,6 +344,9 @@ struct lbm_ctx {
     int slab = 32;
     bool write_check = false;
     int store_policy = LBM_STORE_AUTO;
+    int graph_steps = 0;                         // 0: plain launches
+    hipStream_t cap = nullptr;                   // capture stream of the graphs
+    hipGraphExec_t graphs[2] = {nullptr, nullptr};  // k steps from buffer parity 0 / 1
 
     // Wall-plane densities and ghost psi (Eq. (57)) in a buffer of their own
     // instead of the workspace: the allocation-free step (lbm_step_noalloc).
@@ -580,6 +584,50 @@ lbm_status scratch_of_current_device(unsigned char **out) {
     return LBM_OK;
 }
 
+void drop_graphs(lbm_ctx *c) {
+    for (hipGraphExec_t &g : c->graphs) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+}
+
+// k steps of the current parity from a captured graph (captured on first use
+// on the context's capture stream; the context's counters are advanced here,
+// not by the capture).
+lbm_status graph_steps(lbm_ctx *c, int k) {
+    hipGraphExec_t &ex = c->graphs[c->cur];
+    if (!ex) {
+        if (!c->cap) HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+        const hipStream_t user = c->stream;
+        const int cur0 = c->cur;
+        const int64_t steps0 = c->steps;
+        HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+        c->stream = c->cap;
+        lbm_status s = LBM_OK;
+        for (int j = 0; j < k && s == LBM_OK; ++j) s = one_step(c);
+        c->stream = user;
+        c->cur = cur0;
+        c->steps = steps0;
+        hipGraph_t graph;
+        hipError_t e = hipStreamEndCapture(c->cap, &graph);
+        if (s) {
+            if (e == hipSuccess) (void)hipGraphDestroy(graph);
+            return s;
+        }
+        if (e != hipSuccess) return fail(LBM_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            ex = nullptr;
+            return fail(LBM_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        }
+    }
+    HIP_TRY(hipGraphLaunch(ex, c->stream));
+    c->cur ^= (k & 1);
+    c->steps += k;
+    return LBM_OK;
+}
+
 lbm_status compute_psi_full(lbm_ctx *c) {
     lbm_status s = launch_walls(c, c->state());
     if (s) return s;
@@ -653,6 +701,8 @@ lbm_status lbm_create(const lbm_params *p, void *dev_ws, size_t ws_bytes, void *
 lbm_status lbm_destroy(lbm_ctx *c) {
     if (!c) return fail(LBM_ERR_INVALID_ARG, "ctx is NULL");
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    drop_graphs(c);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
     delete c;
     return LBM_OK;
 }
@@ -700,10 +750,39 @@ lbm_status lbm_init_droplets(lbm_ctx *c, const lbm_droplet *d, int32_t n, double
 lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     if (!c) return fail(LBM_ERR_INVALID_ARG, "ctx is NULL");
     if (nsteps < 0) return fail(LBM_ERR_INVALID_ARG, "nsteps < 0");
-    for (int64_t k = 0; k < nsteps; ++k) {
-        lbm_status s = one_step(c);
-        if (s) return s;
+    const int64_t K = c->p.diag_every;
+    const int G = c->timing ? 0 : c->graph_steps;
+    int64_t left = nsteps;
+    while (left > 0) {
+        // Run up to the next multiple of diag_every (or to the end).
+        int64_t chunk = left;
+        if (K > 0) chunk = std::min<int64_t>(left, K - c->steps % K);
+        for (int64_t done = 0; done < chunk;) {
+            lbm_status s;
+            if (G > 0 && chunk - done >= G) {
+                s = graph_steps(c, G);
+                done += G;
+            } else {
+                s = one_step(c);
+                ++done;
+            }
+            if (s) return s;
+        }
+        left -= chunk;
+        if (K > 0 && c->steps % K == 0) {
+            lbm_diag d;
+            lbm_status s = lbm_diagnostics(c, nullptr, &d);
+            if (s) return s;  // LBM_ERR_NONFINITE names the step
+        }
     }
+    return LBM_OK;
+}
+
+lbm_status lbm_set_graph_steps(lbm_ctx *c, int32_t k) {
+    if (!c) return fail(LBM_ERR_INVALID_ARG, "ctx is NULL");
+    if (k < 0) return fail(LBM_ERR_INVALID_ARG, "graph steps %d < 0", k);
+    if (k != c->graph_steps) drop_graphs(c);
+    c->graph_steps = k;
     return LBM_OK;
 }
 
@@ -859,6 +938,7 @@ lbm_status lbm_set_tile(lbm_ctx *c, const lbm_tile *t) {
     c->tile = *t;
     c->tile.reserved = 0;
     fill_grid(c->g, c->p, c->tile);
+    drop_graphs(c);
     return LBM_OK;
 }
 
@@ -923,6 +1003,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t trials, lbm_tile *best) {
     (void)hipEventDestroy(e1);
     c->tile = bt;
     fill_grid(c->g, c->p, c->tile);
+    drop_graphs(c);
     if (best) *best = bt;
     return LBM_OK;
 }
@@ -960,6 +1041,7 @@ lbm_status lbm_set_step_mode(lbm_ctx *c, int32_t mode, int32_t slab_planes) {
     }
     c->mode = mode;
     c->slab = slab_planes;
+    drop_graphs(c);
     return LBM_OK;
 }
 
@@ -972,6 +1054,7 @@ lbm_status lbm_get_step_mode(const lbm_ctx *c, int32_t *mode, int32_t *slab_plan
 
 lbm_status lbm_set_write_check(lbm_ctx *c, int32_t enable) {
     if (!c) return fail(LBM_ERR_INVALID_ARG, "ctx is NULL");
+    if (c->write_check != (enable != 0)) drop_graphs(c);
     c->write_check = enable != 0;
     return LBM_OK;
 }
@@ -980,6 +1063,7 @@ lbm_status lbm_set_store_policy(lbm_ctx *c, int32_t policy) {
     if (!c) return fail(LBM_ERR_INVALID_ARG, "ctx is NULL");
     if (policy != LBM_STORE_AUTO && policy != LBM_STORE_CACHED && policy != LBM_STORE_STREAM)
         return fail(LBM_ERR_INVALID_ARG, "unknown store policy %d", policy);
+    if (c->store_policy != policy) drop_graphs(c);
     c->store_policy = policy;
     return LBM_OK;
 }
