@@ -59,7 +59,8 @@ lbm_status validate(const lbm_params *p) {
     if (!p) return fail(LBM_ERR_INVALID_ARG, "params is NULL");
     if (p->nx < 1 || p->ny < 1 || p->nz < 1)
         return fail(LBM_ERR_INVALID_ARG, "lattice size %d x %d x %d must be positive", p->nx, p->ny, p->nz);
-    if ((long long)p->nx * p->ny * p->nz * 19LL >= (1LL << 40))
+    // In 128-bit integers: three positive 32-bit factors cannot overflow.
+    if ((__int128)p->nx * p->ny * p->nz * 19 >= ((__int128)1 << 40))
         return fail(LBM_ERR_INVALID_ARG, "lattice too large");
     if (p->wall_z != 0 && p->wall_z != 1) return fail(LBM_ERR_INVALID_ARG, "wall_z must be 0 or 1");
     if (p->wall_z && p->nz < 2) return fail(LBM_ERR_INVALID_ARG, "walls need nz >= 2");

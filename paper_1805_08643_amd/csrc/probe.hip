@@ -149,7 +149,7 @@ lbm_status lbm_probe_march19(const void *src, void *dst, int32_t nx, int32_t ny,
     if (group_bytes != 8 && group_bytes != 16) return fail("group_bytes must be 8 or 16");
     if (nx < 1 || ny < 1 || nz < 1 || tx < 1 || ty < 1 || cz < 1) return fail("sizes must be positive");
     if ((long long)tx * ty > 1024) return fail("tx * ty must be <= 1024");
-    if ((long long)nx * ny * nz * 19 >= (1LL << 40)) return fail("lattice too large");
+    if ((__int128)nx * ny * nz * 19 >= ((__int128)1 << 40)) return fail("lattice too large");
     MarchDesc m{};
     m.nx = nx;
     m.ny = ny;
