@@ -118,7 +118,21 @@ typedef struct lbm_params {
      * returns LBM_ERR_NONFINITE at the first check that finds any, the state
      * left at that step.  0: no checks.  Must be >= 0. */
     int32_t diag_every;
-    int32_t reserved0;
+    /* Readings of the orthogonal comparison operator (LBM_OP_ORTH), which the
+     * paper names but does not print (Secs. IV.A-B); ignored otherwise.
+     * orth_meq: 0 = m_eq = M_orth f_eq of the textbook D3Q19 equilibrium,
+     *   i.e. eps_eq = rho (3 - 11/2 |u|^2) and pi_eq = -p_eq / 2; 1 = the
+     *   free parameters of the Gram-Schmidt D3Q19 model set to
+     *   eps_eq = -475/63 rho |u|^2 and pi_eq = 0 (the stability-tuned choice
+     *   for that basis); the source rows follow the equilibrium
+     *   (S_eps = 2 w_epsj F.u, S_pi = w_xx S_p).
+     * orth_sigma: rows that take the Eq. (16) term: 0 = the e row only
+     *   (x 19; the reading that reproduces the paper's orthogonal Table II:
+     *   rho_V rising with nu); 1 = e (x 19) and eps (x -16), the image of the
+     *   non-orthogonal correction, which equals it for s_eps = s_e. */
+    int32_t orth_meq;
+    int32_t orth_sigma;
+    int32_t reserved1;
 } lbm_params;
 
 /* Launch shape of the fused step: tx * ty threads per block, one thread per

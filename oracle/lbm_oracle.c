@@ -84,6 +84,13 @@ typedef struct {
     int32_t wall_x, wall_y;
     double lid_u[3];
     double lid_rho;
+    /* Orthogonal model, a reading (the paper names the model without printing
+     * it): 0 = m_eq = M_orth f_eq and S = M_orth G as above; 1 = the energy-
+     * square and pi rows of the equilibrium set to eps_eq = -475/63 rho |u|^2
+     * and pi_eq = 0 (the free parameters of the Gram-Schmidt basis chosen for
+     * stability), with their source rows S_eps = 2 (-475/63) F.u, S_pi = 0. */
+    int32_t orth_meq;
+    int32_t reserved3;
 } oracle_params;
 
 static int opp_of(int a) {
@@ -149,6 +156,11 @@ static void meq_of(const oracle_params *p, double rho, const double u[3], double
             for (int a = 0; a < Q; ++a) s += p->M[k * Q + a] * feq[a];
             meq[k] = s;
         }
+        if (p->orth_meq == 1) {
+            meq[2] = -475.0 / 63.0 * rho * u2; /* eps */
+            meq[10] = 0.0;                     /* 3 pi_xx */
+            meq[12] = 0.0;                     /* pi_ww */
+        }
     }
 }
 
@@ -191,6 +203,11 @@ static void source_of(const oracle_params *p, const double u[3], const double F[
             double s = 0.0;
             for (int a = 0; a < Q; ++a) s += p->M[k * Q + a] * G[a];
             S[k] = s;
+        }
+        if (p->orth_meq == 1) {
+            S[2] = 2.0 * (-475.0 / 63.0) * Fu;
+            S[10] = 0.0;
+            S[12] = 0.0;
         }
         double c = 6.0 * p->sigma * Fm2_over_psi2;
         S[1] += p->orth_sig_e * c / (1.0 / p->rates[1] - 0.5);

@@ -42,6 +42,7 @@ class OracleParams(ctypes.Structure):
         ("nu_ratio", ctypes.c_double), ("visc_rho_L", ctypes.c_double), ("visc_rho_V", ctypes.c_double),
         ("wall_x", ctypes.c_int32), ("wall_y", ctypes.c_int32),
         ("lid_u", ctypes.c_double * 3), ("lid_rho", ctypes.c_double),
+        ("orth_meq", ctypes.c_int32), ("reserved3", ctypes.c_int32),
     ]
 
 
@@ -127,6 +128,12 @@ def make_params(cfg: dict, nthreads: int = 0) -> OracleParams:
     p.ghost_rho_min = cfg.get("ghost_rho_min", 0.0)
     ce, ceps = moments.orth_sigma_rows()
     p.orth_sig_e, p.orth_sig_eps = float(ce), float(ceps)
+    # Readings of the orthogonal model: the Eq. (16) term on the e row only
+    # (orth_sigma = 0, the default) or also on the eps row (1); the
+    # alternative equilibrium of the eps and pi rows (orth_meq = 1).
+    if not int(cfg.get("orth_sigma", 0)):
+        p.orth_sig_eps = 0.0
+    p.orth_meq = int(cfg.get("orth_meq", 0))
     r = rates_of(cfg)
     for k in range(Q):
         p.rates[k] = r[k]

@@ -42,7 +42,8 @@ class LbmParams(ctypes.Structure):
         ("nu_ratio", ctypes.c_double), ("visc_rho_L", ctypes.c_double), ("visc_rho_V", ctypes.c_double),
         ("wall_x", ctypes.c_int32), ("wall_y", ctypes.c_int32),
         ("lid_u", ctypes.c_double * 3), ("lid_rho", ctypes.c_double),
-        ("diag_every", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("diag_every", ctypes.c_int32), ("orth_meq", ctypes.c_int32), ("orth_sigma", ctypes.c_int32),
+        ("reserved1", ctypes.c_int32),
     ]
 
 
@@ -355,6 +356,8 @@ def make_params(cfg: dict) -> LbmParams:
         p.lid_u[d] = lu[d]
     p.lid_rho = cfg.get("lid_rho", 1.0)
     p.diag_every = int(cfg.get("diag_every", 0))
+    p.orth_meq = int(cfg.get("orth_meq", 0))
+    p.orth_sigma = int(cfg.get("orth_sigma", 0))
     return p
 
 

@@ -106,6 +106,8 @@ lbm_status validate(const lbm_params *p) {
     for (int d = 0; d < 3; ++d)
         if (!std::isfinite(p->gravity[d])) return fail(LBM_ERR_INVALID_ARG, "gravity not finite");
     if (p->diag_every < 0) return fail(LBM_ERR_INVALID_ARG, "diag_every must be >= 0");
+    if ((p->orth_meq != 0 && p->orth_meq != 1) || (p->orth_sigma != 0 && p->orth_sigma != 1))
+        return fail(LBM_ERR_INVALID_ARG, "orth_meq and orth_sigma must be 0 or 1");
     if (!(p->theta_wall_deg > 0.0 && p->theta_wall_deg < 180.0))
         return fail(LBM_ERR_INVALID_ARG, "theta_wall_deg must be in (0, 180)");
     if (!std::isfinite(p->rho_ref) || !std::isfinite(p->ghost_rho_min))
@@ -144,6 +146,11 @@ PhysD make_phys(const lbm_params &p) {
     d.psi_form = p.psi_form;
     // Density-dependent viscosity: nu = nuV + t dnu, t = (rho - vrhoV) vinv in [0, 1]
     for (int k = 0; k < 3; ++k) d.lid6[k] = 6.0 * p.lid_rho * p.lid_u[k];
+    // Orthogonal operator's free equilibrium parameters and Eq. (16) rows.
+    d.w_eps = p.orth_meq ? 0.0 : 3.0;
+    d.w_epsj = p.orth_meq ? -475.0 / 63.0 : -5.5;
+    d.w_xx = p.orth_meq ? 0.0 : -0.5;
+    d.sig_eps = p.orth_sigma ? 1.0 : 0.0;
     d.visc = p.nu_ratio > 0.0 && p.nu_ratio != 1.0;
     if (d.visc) {
         const double nuL = (1.0 / p.s_nu - 0.5) / 3.0;

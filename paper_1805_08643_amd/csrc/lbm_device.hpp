@@ -53,6 +53,9 @@ struct PhysD {  // host-filled, double
     int visc;   // density-dependent viscosity on
     double nuV, dnu, vrhoV, vinv;
     double lid6[3];  // 6 lid_rho lid_u: moving-face term of a reflected population
+    // Orthogonal operator: eps_eq = rho (w_eps + w_epsj |u|^2), pi_eq = w_xx p_eq,
+    // and the share of the Eq. (16) term the eps row takes (1 or 0).
+    double w_eps, w_epsj, w_xx, sig_eps;
 };
 
 __device__ inline float r_rcp(float v);
@@ -71,6 +74,7 @@ template <class R> struct Phys {
     int visc;
     R nuV, dnu, vrhoV, vinv;
     R lid6[3];
+    R w_eps, w_epsj, w_epsj2, w_xx;
     __device__ inline void load(const PhysD &d) {
         G = (R)d.G;
         a = (R)d.a;
@@ -87,7 +91,11 @@ template <class R> struct Phys {
         s_m = (R)d.s_m;
         // (1 - s/2) * 6 sigma |F_m|^2 / (psi^2 (1/s - 1/2)) = s * 6 sigma |F_m|^2 / psi^2
         ksig_e = (R)(6.0 * d.sigma * d.s_e * d.G * d.G);
-        ksig_eps = (R)(6.0 * d.sigma * d.s_eps * d.G * d.G);
+        ksig_eps = (R)(6.0 * d.sigma * d.s_eps * d.G * d.G * d.sig_eps);
+        w_eps = (R)d.w_eps;
+        w_epsj = (R)d.w_epsj;
+        w_epsj2 = (R)(2.0 * d.w_epsj);
+        w_xx = (R)d.w_xx;
         gx = (R)d.g[0];
         gy = (R)d.g[1];
         gz = (R)d.g[2];
@@ -428,8 +436,10 @@ __device__ inline void collide(R f[Q], R rho, R Fx, R Fy, R Fz, R acc2, const Ph
         for (int a = 0; a < Q; ++a) f[a] += o[a];
     } else {
         // Orthogonal model: m_eq = M_orth f_eq (textbook D3Q19 equilibrium),
-        // S = M_orth G (Guo forcing); Eq. (16) term carried to the e and eps
-        // rows by the image of the non-orthogonal column (19, -16).
+        // S = M_orth G (Guo forcing), or with eps_eq and pi_eq from the
+        // parameters (w_eps, w_epsj, w_xx) and their source rows; Eq. (16)
+        // term carried to the e and eps rows by the image of the
+        // non-orthogonal column (19, -16), or to e only.
         const R ce = (R)1 - (R)0.5 * P.s_e, cE = (R)1 - (R)0.5 * P.s_eps;
         const R cn = (R)1 - (R)0.5 * snu, cq = (R)1 - (R)0.5 * P.s_q;
         const R cp = (R)1 - (R)0.5 * P.s_pi;
@@ -449,7 +459,7 @@ __device__ inline void collide(R f[Q], R rho, R Fx, R Fy, R Fz, R acc2, const Ph
         const R two3 = (R)(2.0 / 3.0);
         dm[0] = (R)0;
         dm[1] = P.s_e * (rho * ((R)(-11) + (R)19 * u2) - e) + ce * (R)38 * Fu + (R)19 * P.ksig_e * acc2;
-        dm[2] = P.s_eps * (rho * ((R)3 - (R)5.5 * u2) - eps) + cE * (R)(-11) * Fu - (R)16 * P.ksig_eps * acc2;
+        dm[2] = P.s_eps * (rho * (P.w_eps + P.w_epsj * u2) - eps) + cE * P.w_epsj2 * Fu - (R)16 * P.ksig_eps * acc2;
         dm[3] = Fx;
         dm[4] = P.s_q * (-two3 * rho * ux - qxm) - cq * two3 * Fx;
         dm[5] = Fy;
@@ -457,9 +467,9 @@ __device__ inline void collide(R f[Q], R rho, R Fx, R Fy, R Fz, R acc2, const Ph
         dm[7] = Fz;
         dm[8] = P.s_q * (-two3 * rho * uz - qzm) - cq * two3 * Fz;
         dm[9] = snu * (rho * dxx - pxx) + cn * Sxx;
-        dm[10] = P.s_pi * ((R)(-0.5) * rho * dxx - ixx) - cp * (R)0.5 * Sxx;
+        dm[10] = P.s_pi * (P.w_xx * rho * dxx - ixx) + cp * P.w_xx * Sxx;
         dm[11] = snu * (rho * dww - pww) + cn * Sww;
-        dm[12] = P.s_pi * ((R)(-0.5) * rho * dww - iww) - cp * (R)0.5 * Sww;
+        dm[12] = P.s_pi * (P.w_xx * rho * dww - iww) + cp * P.w_xx * Sww;
         dm[13] = snu * (rho * ux * uy - pr.p7) + cn * (Fx * uy + Fy * ux);
         dm[14] = snu * (rho * uy * uz - pr.p9) + cn * (Fy * uz + Fz * uy);
         dm[15] = snu * (rho * ux * uz - pr.p8) + cn * (Fx * uz + Fz * ux);
@@ -474,7 +484,8 @@ __device__ inline void collide(R f[Q], R rho, R Fx, R Fy, R Fz, R acc2, const Ph
 }
 
 // Equilibrium populations M^-1 m_eq(rho, u) of either operator.
-template <class R, int OP> __device__ inline void equilibrium(R rho, R ux, R uy, R uz, R f[Q]) {
+template <class R, int OP>
+__device__ inline void equilibrium(R rho, R ux, R uy, R uz, const Phys<R> &P, R f[Q]) {
     const R uxx = ux * ux, uyy = uy * uy, uzz = uz * uz, u2 = uxx + uyy + uzz;
     const R third = (R)(1.0 / 3.0);
     R m[Q];
@@ -505,7 +516,7 @@ template <class R, int OP> __device__ inline void equilibrium(R rho, R ux, R uy,
         const R dxx = (R)2 * uxx - uyy - uzz, dww = uyy - uzz;
         m[0] = rho;
         m[1] = rho * ((R)(-11) + (R)19 * u2);
-        m[2] = rho * ((R)3 - (R)5.5 * u2);
+        m[2] = rho * (P.w_eps + P.w_epsj * u2);
         m[3] = rho * ux;
         m[4] = -two3 * rho * ux;
         m[5] = rho * uy;
@@ -513,9 +524,9 @@ template <class R, int OP> __device__ inline void equilibrium(R rho, R ux, R uy,
         m[7] = rho * uz;
         m[8] = -two3 * rho * uz;
         m[9] = rho * dxx;
-        m[10] = (R)(-0.5) * rho * dxx;
+        m[10] = P.w_xx * rho * dxx;
         m[11] = rho * dww;
-        m[12] = (R)(-0.5) * rho * dww;
+        m[12] = P.w_xx * rho * dww;
         m[13] = rho * ux * uy;
         m[14] = rho * uy * uz;
         m[15] = rho * ux * uz;

@@ -1734,7 +1734,7 @@ __global__ void k_init_fields(typename Storage<S>::T *__restrict__ A, const doub
          i += (long long)gridDim.x * blockDim.x) {
         const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((long long)nx * ny));
         R v[Q];
-        equilibrium<R, OP>((R)rho[i], (R)u[i], (R)u[g.N + i], (R)u[2 * g.N + i], v);
+        equilibrium<R, OP>((R)rho[i], (R)u[i], (R)u[g.N + i], (R)u[2 * g.N + i], P, v);
         scatter_node<S, WALL>(A, g, P, x, y, z, v);
     }
 }
@@ -1788,7 +1788,7 @@ __global__ void k_init_droplets(typename Storage<S>::T *__restrict__ A, DropletS
         double rho, u[3];
         droplet_rho_u(D, g, x, y, z, rho, u);
         R v[Q];
-        equilibrium<R, OP>((R)rho, (R)u[0], (R)u[1], (R)u[2], v);
+        equilibrium<R, OP>((R)rho, (R)u[0], (R)u[1], (R)u[2], P, v);
         scatter_node<S, WALL>(A, g, P, x, y, z, v);
     }
 }

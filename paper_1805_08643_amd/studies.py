@@ -108,10 +108,15 @@ def _params(n, **kw):
 # --------------------------------------------------------------------------
 def _phase_separation(nu, op, n, seed, storage):
     cfg = _params(n, op=op, tau_nu=tau_for_nu(nu), storage=storage, **EXP_PSI, **PAPER_RATES)
+    return _phase_separation_cfg(cfg, seed)
+
+
+def _phase_separation_cfg(cfg, seed):
+    n3 = cfg["nx"] * cfg["ny"] * cfg["nz"]
     rng = np.random.default_rng(seed)
-    rho = 1.0 - rng.uniform(0.0, 10.0, n ** 3) / 5000.0
+    rho = 1.0 - rng.uniform(0.0, 10.0, n3) / 5000.0
     lat = _lattice(cfg)
-    lat.init_fields(rho, np.zeros((3, n ** 3)))
+    lat.init_fields(rho, np.zeros((3, n3)))
     return lat
 
 
@@ -345,6 +350,75 @@ def table2(ops=("nonorth", "orth"), nus=(0.01, 1.0 / 30.0, 0.05, 0.1, 0.15), ste
             lat.close()
             out.append(_emit(dict(study="table2", op=op, nu=nu, inv_s_nu=tau_for_nu(nu), steps=steps,
                                   start=f"state after {steps} steps at nu={warm_nu}", **obs)))
+    return out
+
+
+ORTH_READINGS = {
+    # name: extra parameters of the orthogonal operator
+    "meq_Morth_sigma_e_eps": dict(orth_meq=0, orth_sigma=1),
+    "meq_Morth_sigma_e": dict(orth_meq=0, orth_sigma=0),
+    "meq_tuned_sigma_e_eps": dict(orth_meq=1, orth_sigma=1),
+    "meq_tuned_sigma_e": dict(orth_meq=1, orth_sigma=0),
+    "meq_Morth_sigma_e_eps_seps_se": dict(orth_meq=0, orth_sigma=1, s_eps="s_e"),
+    "meq_Morth_sigma_e_sm198": dict(orth_meq=0, orth_sigma=0, s_m=1.98),
+    "meq_Morth_sigma_e_spi_snu": dict(orth_meq=0, orth_sigma=0, s_pi="s_nu", s_eps="s_nu"),
+}
+
+
+def orth_readings(readings=tuple(ORTH_READINGS), nus=(0.01, 0.05, 0.1, 0.15), steps=30000, n=120, warm_nu=0.1,
+                  stab_nus=(1e-3, 2e-3), stab_steps=8000, chunk=250, seed=1805):
+    """Readings of the orthogonal comparison operator against the two
+    observations the paper prints for it: Table II (C-S at T = 0.6 T_c, the
+    120^3 droplet, rho_V rising with nu: 0.00313 / 0.00319 / 0.00321 /
+    0.00323) and the stability of the Table I phase separation at
+    nu = 2e-3 (diverging at 1e-3).  Table II runs start cold except at
+    nu = 0.01, which continues the nu = 0.1 state (a cold start diverges for
+    every reading, as for the non-orthogonal model)."""
+    import lbm_inputs as li
+    rl0, rv0 = li.coexistence(0.6)
+    c = (n / 2, n / 2, n / 2)
+    out = []
+    for name in readings:
+        def rates(nu):
+            extra = dict(ORTH_READINGS[name])
+            for k, v in list(extra.items()):
+                if v == "s_e":
+                    extra[k] = PAPER_RATES["s_e"]
+                elif v == "s_nu":
+                    extra[k] = 1.0 / tau_for_nu(nu)
+            return {**PAPER_RATES, **extra}
+
+        def cfg_for(nu):
+            return _params(n, op="orth", T_over_Tc=0.6, eos_a=0.25, sigma=0.105, tau_nu=tau_for_nu(nu),
+                           storage="f64", **rates(nu))
+        warm = None
+        for nu in sorted(nus, reverse=True):
+            lat = _lattice(cfg_for(nu))
+            start = "cold"
+            if nu < 0.05 and warm is not None:
+                lat.load_state(warm)
+                start = f"state after {steps} steps at nu={warm_nu}"
+            else:
+                lat.init_droplets([dict(center=c, r0=40.0)], rl0, rv0, 5.0)
+            lat.step(steps)
+            obs = _droplet(lat, c, 40.0, 5.0)
+            if nu == warm_nu:
+                warm = lat.save_state()
+            lat.close()
+            out.append(_emit(dict(study="orth_readings", reading=name, table="II", nu=nu, start=start, **obs)))
+        for nu in stab_nus:
+            cfg = _params(n, op="orth", tau_nu=tau_for_nu(nu), storage="f64", **EXP_PSI, **rates(nu))
+            lat = _phase_separation_cfg(cfg, seed)
+            diverged = None
+            for k in range(stab_steps // chunk):
+                lat.step(chunk)
+                d = lat.diagnostics()
+                if d["nonfinite"] or not math.isfinite(d["max_u"]) or d["max_u"] > 0.5:
+                    diverged = (k + 1) * chunk
+                    break
+            lat.close()
+            out.append(_emit(dict(study="orth_readings", reading=name, table="stability", nu=nu,
+                                  steps=stab_steps, diverged_by_step=diverged, max_u=d["max_u"])))
     return out
 
 
@@ -610,7 +684,8 @@ def precision(steps=(100, 500, 1000, 2000), n=256, crop=64):
     return out
 
 
-STUDIES = {f.__name__: f for f in (table1, stability, laplace, spurious, contact, flat, table2, viscosity_ratio,
+STUDIES = {f.__name__: f for f in (table1, stability, laplace, spurious, contact, flat, table2, orth_readings,
+                                   viscosity_ratio,
                                    cavity_cost, cavity_mach, laplace_cs, contact_cs, precision, throughput)}
 
 

@@ -60,6 +60,8 @@ int main() {
         {"gravity inf", [](lbm_params &q) { q.gravity[2] = std::numeric_limits<double>::infinity(); },
          LBM_ERR_INVALID_ARG},
         {"diag_every<0", [](lbm_params &q) { q.diag_every = -1; }, LBM_ERR_INVALID_ARG},
+        {"orth_meq=2", [](lbm_params &q) { q.orth_meq = 2; }, LBM_ERR_INVALID_ARG},
+        {"orth_sigma<0", [](lbm_params &q) { q.orth_sigma = -1; }, LBM_ERR_INVALID_ARG},
         {"lid without wall", [](lbm_params &q) { q.lid_u[0] = 0.1; }, LBM_ERR_INVALID_ARG},
         {"x walls multiphase", [](lbm_params &q) { q.wall_x = 1; }, LBM_ERR_UNSUPPORTED},
         {"five planes > 4 GiB", [](lbm_params &q) { q.nx = q.ny = 1024; q.nz = 512; q.storage = LBM_STORE_F64; },

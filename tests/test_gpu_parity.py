@@ -939,3 +939,27 @@ def test_maximum_size_lattice(storage):
     x, y, z = idx % nx, (idx // nx) % ny, idx // (nx * ny)
     src = ((z % P) * 64 + y % 64) * 64 + x % 64
     assert np.array_equal(got, fs[:, src])
+
+
+# ---------------------------------------------------------------------------
+# Readings of the orthogonal comparison operator: the alternative equilibrium
+# of its eps and pi rows (orth_meq = 1) and the Eq. (16) term on the e row
+# only (orth_sigma = 1), against the oracle with the same reading.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("meq,sig", [(1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("name", ["droplet_32", "walls_40x33x19_60deg"])
+def test_orth_readings_parity(name, meq, sig):
+    cfg, rho, u, tile = _case(name, "orth", "f64")
+    cfg = dict(cfg, orth_meq=meq, orth_sigma=sig)
+    cps = [0, 1, 5, 50]
+    got = gpu_states(cfg, rho, u, cps, tile)
+    want = oracle_states(cfg, rho, u, cps)
+    for s, g, w in zip(cps, got, want):
+        e = rho_err(g, w)
+        print(f"  step {s}: err {e:.3e}")
+        assert e < 1e-12, (s, e)
+    cfg32 = dict(cfg, storage="f32")
+    got = gpu_states(cfg32, rho, u, [1, 10], None, "split")
+    want = oracle_states(cfg32, rho, u, [1, 10])
+    for s, g, w in zip([1, 10], got, want):
+        assert rho_err(g, w) < fp32_bound(s), s

@@ -145,3 +145,31 @@ def test_rates_layout(op):
         d = dict(zip(names, r))
         assert d["e"] == 1.1 and d["eps"] == 1.5 and d["mx"] == 1.6 and d["qy"] == 1.2
         assert d["pxy"] == d["3pxx"] == d["pww"] == 1.0 and d["3pixx"] == d["piww"] == 1.4
+
+
+def test_orth_equilibrium_rows_in_closed_form():
+    """The orthogonal model's default equilibrium and forcing moments
+    (M_orth f_eq with the textbook D3Q19 f_eq, M_orth G with Guo's G) have the
+    closed forms that the kernel evaluates with free parameters:
+    eps_eq = rho (3 - 11/2 |u|^2), 3pi_xx = -(1/2) 3p_xx, pi_ww = -(1/2) p_ww,
+    S_eps = -11 F.u, and the pi source rows -1/2 of the p source rows.  The
+    other reading of the model (orth_meq = 1) changes exactly these three
+    rows (and their sources) to w_eps = 0, w_epsj = -475/63, w_xx = 0."""
+    M = np.array(moments.orth_M(), dtype=float)
+    E = np.array(moments.VELOCITIES, dtype=float)
+    w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+    names = moments.ORTH_ROW_NAMES
+    ie, ipxx, iixx, ipww, iiww = (names.index(n) for n in ("eps", "3pxx", "3pixx", "pww", "piww"))
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        rho = rng.uniform(0.1, 2.0)
+        u = rng.uniform(-0.1, 0.1, 3)
+        F = rng.uniform(-1e-2, 1e-2, 3)
+        eu, eF = E @ u, E @ F
+        feq = w * rho * (1 + 3 * eu + 4.5 * eu ** 2 - 1.5 * u @ u)
+        G = w * (3 * (eF - F @ u) + 9 * eu * eF)
+        m, S = M @ feq, M @ G
+        assert abs(m[ie] - rho * (3 - 5.5 * (u @ u))) < 1e-13
+        assert abs(m[iixx] + 0.5 * m[ipxx]) < 1e-13 and abs(m[iiww] + 0.5 * m[ipww]) < 1e-13
+        assert abs(S[ie] - 2 * (-5.5) * (F @ u)) < 1e-15
+        assert abs(S[iixx] + 0.5 * S[ipxx]) < 1e-15 and abs(S[iiww] + 0.5 * S[ipww]) < 1e-15

@@ -131,7 +131,13 @@ def _bgk_step_reference(p_or, cfg, f, s, nonorth):
             GB[a] = W_STD[a] * (3 * (eF - uF) + 9 * eu * eF)
     Fm2 = (Fm * Fm).sum(0)
     X = 6 * cfg["sigma"] * Fm2 / (psi * psi) / (1 / s - 0.5)
-    v4 = np.array([-1.0] + [1 / 6] * 6 + [0.0] * 12)
+    if nonorth or cfg.get("orth_sigma", 0):
+        v4 = np.array([-1.0] + [1 / 6] * 6 + [0.0] * 12)
+    else:
+        # orthogonal model with the term on its e row only (19 X there):
+        # velocity-space image 19 X (19 |e|^2 - 30) / 2394 per direction
+        e2 = (E * E).sum(1)
+        v4 = 19.0 * (19.0 * e2 - 30.0) / 2394.0
     post = f4 - s * (f4 - fB) + (1 - s / 2) * (GB + v4[:, None, None, None] * X[None])
     out = np.empty_like(post)
     for a in range(Q):
@@ -139,15 +145,24 @@ def _bgk_step_reference(p_or, cfg, f, s, nonorth):
     return out.reshape(Q, -1)
 
 
-@pytest.mark.parametrize("op", ["nonorth", "orth"])
+@pytest.mark.parametrize("op", ["nonorth", "orth", "orth_sigma_e_eps"])
 @pytest.mark.parametrize("s", [1.3, 0.8])
 def test_equal_rates_reduce_to_bgk(op, s):
-    cfg = li.params(4, 4, 4, op=op, T_over_Tc=0.8, sigma=0.105, rates=[s] * Q)
+    """With all rates equal, each operator is a BGK step with Guo forcing plus
+    the Eq. (16) term carried to velocity space.  The orthogonal model with
+    the term on its e and eps rows applies exactly the non-orthogonal
+    correction; with the term on e only (the default reading) its image is
+    19 X (19 |e|^2 - 30) / 2394."""
+    cfg = li.params(4, 4, 4, op=op.split("_")[0], T_over_Tc=0.8, sigma=0.105, rates=[s] * Q,
+                    orth_sigma=1 if op.endswith("e_eps") else 0)
     p = ref.make_params(cfg)
     f = li.random_populations(4, 4, 4, seed=7, lo=0.0005, hi=0.02)
     got = ref.step(p, f, 1)
     want = _bgk_step_reference(p, cfg, f, s, op == "nonorth")
     np.testing.assert_allclose(got, want, rtol=1e-13, atol=1e-16)
+    if op != "nonorth":  # the two orthogonal readings differ by the eps-row term
+        other = _bgk_step_reference(p, dict(cfg, orth_sigma=1 - cfg["orth_sigma"]), f, s, False)
+        assert not np.allclose(got, other, rtol=1e-10, atol=0)
 
 
 def test_bgk_reference_rejects_planted_error():
@@ -247,11 +262,14 @@ def _single_phase(nx, ny, nz, op, s_e, s_nu, **kw):
                      tau_nu=1.0 / s_nu, **kw)
 
 
-@pytest.mark.parametrize("op", ["nonorth", "orth"])
+@pytest.mark.parametrize("op", ["nonorth", "orth", "orth_meq1"])
 def test_shear_wave_decay_matches_eq54(op):
-    """u_x = U sin(k y) decays at nu k^2 with nu = c_s^2 (1/s_nu - 1/2)."""
+    """u_x = U sin(k y) decays at nu k^2 with nu = c_s^2 (1/s_nu - 1/2); for
+    the orthogonal operator also with the other equilibrium reading (the
+    stress rows, which set the shear viscosity, are the same)."""
     L, s_nu = 64, 1.2
-    cfg = _single_phase(1, L, 1, op, s_e=0.9, s_nu=s_nu)
+    cfg = _single_phase(1, L, 1, op.split("_")[0], s_e=0.9, s_nu=s_nu)
+    cfg["orth_meq"] = 1 if op.endswith("meq1") else 0
     p = ref.make_params(cfg)
     k = 2 * math.pi / L
     y = np.arange(L)
