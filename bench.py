@@ -93,15 +93,16 @@ def copy_probe(reps=5, quiet=False, nbytes=1 << 30, streaming=True, blocks=32768
     return out
 
 
-def ceiling_probe(reps=10, quick=False):
-    """Rates of pure data movement at the byte volume of one FP32 step of the
-    256^3 lattice (19 planes of 256^3 values, 1.27 GB read and 1.27 GB
-    written), in the access patterns of the step kernels.  quick: only the
-    fastest flat copy and 19-plane stream (streaming stores)."""
+def ceiling_probe(reps=10, quick=False, storage="f32"):
+    """Rates of pure data movement at the byte volume of one step of the
+    256^3 lattice (19 planes of 256^3 values: 1.27 GB read and 1.27 GB
+    written in FP32, half that in F16S), in the access patterns of the step
+    kernels.  quick: only the fastest flat copy and 19-plane stream
+    (streaming stores)."""
     import torch
 
     from paper_1805_08643_amd import probe
-    n, s = 256, 4
+    n, s = 256, (2 if storage == "f16s" else 4)
     plane_bytes = n ** 3 * s
     total = 19 * plane_bytes
     src = torch.ones(total // 4, dtype=torch.float32, device="cuda")
@@ -127,8 +128,11 @@ def ceiling_probe(reps=10, quick=False):
             ms = _timed(lambda: probe.lbm_probe_stream19(src.data_ptr(), dst.data_ptr(), plane_bytes, gb, nt, 0, st),
                         reps)
             rec("stream19", ms, group_bytes=gb, streaming_stores=nt, blocks=8192)
-        # the split step's FP32 tiles: 128 x 4 nodes (64 x 4 groups of two), z runs of 128 planes
-        for gb, tx, ty, cz in ((8, 64, 4, 128), (16, 32, 4, 128), (8, 64, 8, 64), (8, 128, 2, 128)):
+        # the split step's tiles: FP32 128 x 4 nodes (64 x 4 groups of two) with z runs of 128 planes,
+        # F16S 128 x 8 nodes (32 x 8 groups of four) with z runs of 64
+        tiles = ((8, 64, 4, 128), (16, 32, 4, 128), (8, 64, 8, 64), (8, 128, 2, 128)) if s == 4 else \
+            ((8, 32, 8, 64), (16, 16, 8, 64), (8, 64, 4, 64), (8, 64, 4, 128))
+        for gb, tx, ty, cz in tiles:
             nodes_per_group = gb // s
             ms = _timed(lambda: probe.lbm_probe_march19(src.data_ptr(), dst.data_ptr(), n // nodes_per_group, n, n,
                                                         gb, tx, ty, cz, nt, st), reps)
@@ -137,7 +141,7 @@ def ceiling_probe(reps=10, quick=False):
     assert torch.equal(src[-1024:], dst[-1024:])
     del src, dst
     torch.cuda.empty_cache()
-    return {"bytes_read": total, "bytes_written": total, "rows": rows,
+    return {"storage": storage, "bytes_read": total, "bytes_written": total, "rows": rows,
             "best_GBps": max(r["GBps_read_plus_write"] for r in rows)}
 
 
@@ -394,7 +398,7 @@ def main():
         copy_probe()
         return
     if a.ceiling_probe:
-        print(json.dumps(ceiling_probe()), flush=True)
+        print(json.dumps(ceiling_probe(storage="f16s" if a.storage == "f16s" else "f32")), flush=True)
         return
     from paper_1805_08643_amd.binding import algorithmic_bytes_per_node
 
