@@ -5,7 +5,7 @@ T = 0.6 T_c, a = 0.25, droplets of radius 30 approaching at 0.05), FP32
 population storage, non-orthogonal operator.  One step = one lattice update
 of every node (all of the fused kernel's work).  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage f32|f16s|f64]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage f32|f16s|f16n|f64]
                   [--op nonorth|orth] [--no-cpu] [--no-variants]
 """
 from __future__ import annotations
@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--storage", default="f32", choices=["f32", "f16s", "f64"])
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16s", "f16n", "f64"])
     ap.add_argument("--op", default="nonorth", choices=["nonorth", "orth"])
     ap.add_argument("--workload", default=WORKLOAD, choices=sorted(WORKLOADS) + ["batch_256"],
                     help="lattice to time (default: the 256^3 two-droplet workload); batch_256 times only the "
@@ -398,7 +398,7 @@ def main():
         copy_probe()
         return
     if a.ceiling_probe:
-        print(json.dumps(ceiling_probe(storage="f16s" if a.storage == "f16s" else "f32")), flush=True)
+        print(json.dumps(ceiling_probe(storage="f16s" if a.storage in ("f16s", "f16n") else "f32")), flush=True)
         return
     from paper_1805_08643_amd.binding import algorithmic_bytes_per_node
 
@@ -440,7 +440,7 @@ def main():
         for st, op, md in [("f32", "nonorth", "fused"), ("f32", "nonorth", "pairs"), ("f32", "nonorth", "split"),
                            ("f16s", "nonorth", "fused"),
                            ("f16s", "nonorth", "pairs"), ("f16s", "nonorth", "quads"), ("f16s", "nonorth", "split"),
-                           ("f32", "orth", None),
+                           ("f16n", "nonorth", "split"), ("f32", "orth", None),
                            ("f64", "nonorth", "fused")]:
             key = f"{st}_{op}_{md or 'default'}"
             if (st, op) == (a.storage, a.op) and md in (None, mode):

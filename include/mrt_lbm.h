@@ -61,7 +61,17 @@ enum { LBM_OP_NONORTH = 0, /* Eqs. (7)-(14), (16): the paper's model */
  * evaluated exactly from the FP32 population and rounded once to nearest
  * even; loading gives h_a 2^-f16_exp + w_a rho_ref rounded once to FP32.  The
  * power-of-two factor only moves h into the normal range of binary16. */
-enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16S = 2 };
+enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16S = 2, LBM_STORE_F16N = 3 };
+/* F16N (binary16 relative to the pulling node) stores every population that
+ * arrives at node x as h_a = (fbar*_a - w_a rt(x)) * 2^f16_exp in binary16,
+ * rounded as F16S, where rt(x) is the density of x at the step that wrote the
+ * state (the sum of its 19 populations in FP32), itself rounded to binary16 and
+ * kept in a twentieth plane: element 19 N + i of the state holds rt of node i.
+ * The shift w_a rt(x) is one FP32 product.  A node's populations then differ
+ * from their shifts only by what streaming and collision changed in one step,
+ * instead of by the whole liquid-vapour density contrast of F16S.  rho_ref is
+ * ignored.  F16N runs the split step only (nx a multiple of 4, walls only on
+ * z, no batches); its step moves 40 instead of 38 values of 2 bytes per node. */
 
 /* Pseudopotential form (text after Eq. (15)). */
 enum { LBM_PSI_SQRT_CS = 0, /* psi = sqrt(2 (p_EOS - rho/3) / G), C-S p_EOS, Eq. (58) */
@@ -74,9 +84,10 @@ typedef struct lbm_params {
     int32_t op;             /* LBM_OP_* */
     int32_t storage;        /* LBM_STORE_* */
     int32_t psi_form;       /* LBM_PSI_* */
-    int32_t f16_exp;        /* F16S: stored value is (fbar - w rho_ref) * 2^f16_exp,
-                               in [-24, 24]; pick it so the largest |fbar - w rho_ref|
-                               scaled stays below 2^15 (ignored otherwise) */
+    int32_t f16_exp;        /* F16S, F16N: stored value is (fbar - w rho_ref) * 2^f16_exp
+                               (F16N: w rt(x)), in [-24, 24]; pick it so the largest
+                               |fbar - w rho_ref| scaled stays below 2^15 (ignored
+                               otherwise) */
     double rho_ref;         /* F16S shift density (ignored otherwise) */
     /* Relaxation rates, Eq. (11); each in (0, 2).  ORTH also uses s_eps (energy
      * square) and s_m (cubic m_x,y,z rows). */
@@ -176,7 +187,7 @@ typedef struct lbm_batch lbm_batch;
 void lbm_params_default(lbm_params *p);
 
 /* Device bytes needed by lbm_create for these parameters: two population
- * buffers of 19 N elements, a psi buffer of N, wall planes and diagnostics
+ * buffers of 19 N elements (20 N for F16N), a psi buffer of N, wall planes and diagnostics
  * partials, each 256-byte aligned. */
 lbm_status lbm_workspace_bytes(const lbm_params *p, size_t *bytes);
 
@@ -223,7 +234,8 @@ lbm_status lbm_set_graph_steps(lbm_ctx *ctx, int32_t k);
  * in dev_src to dev_dst, with no context and no allocation of host or device
  * memory.
  *   p: the lattice parameters (validated as by lbm_create).
- *   dev_src, dev_dst: distinct device buffers of 19 N storage elements each,
+ *   dev_src, dev_dst: distinct device buffers of 19 N storage elements each
+ *     (20 N for F16N),
  *     256-byte aligned, in the layout of the raw state (lbm_save_state):
  *     element a * N + i holds direction a of node i, in the storage format of
  *     p->storage; owned by the caller.  dev_src is read, dev_dst written.
@@ -286,9 +298,9 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t trials, lbm_tile *best);
  * groups of nodes (four F16S or two FP32 per thread) with the block split by
  * wave into pullers (global loads, psi, populations into LDS) running three
  * planes ahead of colliders (collision from LDS, stores), so memory and
- * arithmetic overlap; F16S with nx a multiple of 4 or FP32 with even nx; tile
+ * arithmetic overlap; F16S or F16N with nx a multiple of 4 or FP32 with even nx; tile
  * width a multiple of the group size and at most 256, at most 256 groups and
- * 1024 nodes, (tx + 2)(ty + 2) <= 1548, and a halo ring 2 (tx + ty) + 4 of at
+ * 1024 nodes, (tx + 2)(ty + 2) <= 1548 (1300 for F16N), and a halo ring 2 (tx + ty) + 4 of at
  * most 512 nodes for F16S or 768 for FP32 (tuned: 128 x 8 nodes for F16S,
  * 128 x 4 for FP32).
  * A mode that does not apply

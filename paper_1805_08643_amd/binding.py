@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "lib", "libmrtlbm.so")
 
 Q = 19
 OP = {"nonorth": 0, "orth": 1}
-STORAGE = {"f64": 0, "f32": 1, "f16s": 2}
+STORAGE = {"f64": 0, "f32": 1, "f16s": 2, "f16n": 3}
 PSI = {"sqrt_cs": 0, "exp": 1}
 STEP_MODES = {"fused": 0, "slabs": 1, "pairs": 2, "quads": 3, "split": 4}
 STORE_POLICIES = {"auto": 0, "cached": 1, "stream": 2}
@@ -620,9 +620,16 @@ class Batch:
 
 
 def storage_bytes(storage: str) -> int:
-    return {"f64": 8, "f32": 4, "f16s": 2}[storage]
+    return {"f64": 8, "f32": 4, "f16s": 2, "f16n": 2}[storage]
+
+
+def planes(storage: str) -> int:
+    """Values per node of a population array: 19 directions, plus the
+    reference density of F16N."""
+    return 20 if storage == "f16n" else 19
 
 
 def algorithmic_bytes_per_node(storage: str) -> int:
-    """19 population reads + 19 writes per lattice update."""
-    return 38 * storage_bytes(storage)
+    """19 population reads + 19 writes per lattice update (F16N: 20 + 20,
+    with the reference densities)."""
+    return 2 * planes(storage) * storage_bytes(storage)

@@ -51,6 +51,9 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 size_t elem_bytes(int storage) { return storage == LBM_STORE_F64 ? 8 : (storage == LBM_STORE_F32 ? 4 : 2); }
+// Storage elements per node of a population array (19 directions, plus the
+// reference plane of F16N).
+size_t pop_elems(int storage) { return (size_t)planes_of(storage); }
 size_t real_bytes(int storage) { return storage == LBM_STORE_F64 ? 8 : 4; }
 
 bool rate_ok(double s) { return std::isfinite(s) && s > 0.0 && s < 2.0; }
@@ -65,8 +68,11 @@ lbm_status validate(const lbm_params *p) {
     if (p->wall_z != 0 && p->wall_z != 1) return fail(LBM_ERR_INVALID_ARG, "wall_z must be 0 or 1");
     if (p->wall_z && p->nz < 2) return fail(LBM_ERR_INVALID_ARG, "walls need nz >= 2");
     if (p->op != LBM_OP_NONORTH && p->op != LBM_OP_ORTH) return fail(LBM_ERR_INVALID_ARG, "unknown op %d", p->op);
-    if (p->storage < LBM_STORE_F64 || p->storage > LBM_STORE_F16S)
+    if (p->storage < LBM_STORE_F64 || p->storage > LBM_STORE_F16N)
         return fail(LBM_ERR_INVALID_ARG, "unknown storage %d", p->storage);
+    if (p->storage == LBM_STORE_F16N && (p->nx % 4 || p->wall_x || p->wall_y))
+        return fail(LBM_ERR_UNSUPPORTED, "F16N storage runs the split step only: nx must be a multiple of 4 (got "
+                    "%d) and walls only on z", p->nx);
     if (p->psi_form != LBM_PSI_SQRT_CS && p->psi_form != LBM_PSI_EXP)
         return fail(LBM_ERR_INVALID_ARG, "unknown psi_form %d", p->psi_form);
     if (p->f16_exp < -24 || p->f16_exp > 24) return fail(LBM_ERR_INVALID_ARG, "f16_exp %d outside [-24, 24]", p->f16_exp);
@@ -142,7 +148,7 @@ PhysD make_phys(const lbm_params &p) {
     d.tan_wall = std::tan((90.0 - p.theta_wall_deg) * M_PI / 180.0);
     d.ghost_rho_min = p.ghost_rho_min;
     d.rho_ref = p.storage == LBM_STORE_F16S ? p.rho_ref : 0.0;
-    d.h_exp = p.storage == LBM_STORE_F16S ? p.f16_exp : 0;
+    d.h_exp = (p.storage == LBM_STORE_F16S || p.storage == LBM_STORE_F16N) ? p.f16_exp : 0;
     d.psi_form = p.psi_form;
     // Density-dependent viscosity: nu = nuV + t dnu, t = (rho - vrhoV) vinv in [0, 1]
     for (int k = 0; k < 3; ++k) d.lid6[k] = 6.0 * p.lid_rho * p.lid_u[k];
@@ -169,7 +175,7 @@ struct Layout {
 Layout layout_of(const lbm_params &p) {
     const size_t N = (size_t)p.nx * p.ny * p.nz;
     const size_t plane = (size_t)p.nx * p.ny;
-    const size_t pops = align_up(19 * N * elem_bytes(p.storage));
+    const size_t pops = align_up(pop_elems(p.storage) * N * elem_bytes(p.storage));
     Layout L{};
     size_t off = 0;
     L.A = off;
@@ -201,7 +207,7 @@ int block_threads(int tx, int ty, int npt = 1) {
 // Nodes per thread of a step mode (the split mode moves 8 bytes per access:
 // four F16S or two FP32 nodes).
 int npt_of(int mode, int storage) {
-    if (mode == LBM_STEP_SPLIT) return storage == ST_F16S ? 4 : 2;
+    if (mode == LBM_STEP_SPLIT) return (storage == ST_F16S || storage == ST_F16N) ? 4 : 2;
     return mode == LBM_STEP_QUADS ? 4 : (mode == LBM_STEP_PAIRS ? 2 : 1);
 }
 
@@ -213,15 +219,20 @@ constexpr size_t kMaxStepLds = 65536;
 // and the colliders' (one for F16S groups of four, two for FP32 pairs).
 int split_rounds(int npt) { return npt == 4 ? 2 : 3; }
 
-lbm_status check_split_tile(const lbm_tile &t, int npt) {
+// Slots of the split step's psi ring: (tx + 2)(ty + 2) of a tile at most
+// (F16N's LDS also holds a ring of reference densities, so its tiles are smaller).
+int split_sp(int storage) { return storage == ST_F16N ? SPLIT_SP_N : SPLIT_SP; }
+
+lbm_status check_split_tile(const lbm_tile &t, int npt, int storage) {
     // The halo ring, 2 (tx + 2) + 2 ty nodes, takes at most split_rounds(npt)
     // rounds of 256 threads (pullers, then colliders once for F16S, twice for FP32).
     const int ring_max = split_rounds(npt) * SPLIT_ROLE / 2 - 2;
+    const int sp = split_sp(storage);
     if (t.tx < npt || t.ty < 1 || t.cz < 1 || t.tx % npt || t.tx > SPLIT_TX || (t.tx / npt) * t.ty > SPLIT_ROLE ||
-        t.tx * t.ty > SPLIT_NODES || (t.tx + 2) * (t.ty + 2) > SPLIT_SP || t.tx + t.ty > ring_max)
+        t.tx * t.ty > SPLIT_NODES || (t.tx + 2) * (t.ty + 2) > sp || t.tx + t.ty > ring_max)
         return fail(LBM_ERR_INVALID_ARG, "split mode needs a tile width that is a multiple of %d and at most %d, at "
                     "most %d groups of %d nodes, %d nodes, (tx + 2)(ty + 2) <= %d and tx + ty <= %d; got %d x %d x %d",
-                    npt, SPLIT_TX, SPLIT_ROLE, npt, SPLIT_NODES, SPLIT_SP, ring_max, t.tx, t.ty, t.cz);
+                    npt, SPLIT_TX, SPLIT_ROLE, npt, SPLIT_NODES, sp, ring_max, t.tx, t.ty, t.cz);
     return LBM_OK;
 }
 
@@ -236,8 +247,8 @@ bool stream_stores(int policy, size_t pop_bytes) {
 bool split_ring2(int tx, int ty) { return 2 * (tx + 2) + 2 * ty > SPLIT_ROLE; }
 
 // Most rows a split tile of width tx can have.
-int split_rows(int tx, int npt) {
-    return std::max(1, std::min({SPLIT_ROLE / (tx / npt), SPLIT_NODES / tx, SPLIT_SP / (tx + 2) - 2,
+int split_rows(int tx, int npt, int storage) {
+    return std::max(1, std::min({SPLIT_ROLE / (tx / npt), SPLIT_NODES / tx, split_sp(storage) / (tx + 2) - 2,
                                  split_rounds(npt) * SPLIT_ROLE / 2 - 2 - tx}));
 }
 
@@ -311,19 +322,22 @@ lbm_tile wide_tile(int nx, int ny, int nz, int npt) {
 }
 
 bool box_walls(const lbm_params &p) { return p.wall_x || p.wall_y; }
-bool pairs_apply(const lbm_params &p) { return p.storage != ST_F64 && p.nx % 2 == 0 && !box_walls(p); }
+bool pairs_apply(const lbm_params &p) {
+    return (p.storage == ST_F32 || p.storage == ST_F16S) && p.nx % 2 == 0 && !box_walls(p);
+}
 bool quads_apply(const lbm_params &p) { return p.storage == ST_F16S && p.nx % 4 == 0 && !box_walls(p); }
 bool split_apply(const lbm_params &p) {
-    return !box_walls(p) && ((p.storage == ST_F16S && p.nx % 4 == 0) || (p.storage == ST_F32 && p.nx % 2 == 0));
+    return !box_walls(p) && (((p.storage == ST_F16S || p.storage == ST_F16N) && p.nx % 4 == 0) ||
+                             (p.storage == ST_F32 && p.nx % 2 == 0));
 }
 
 // Default tile of the split mode: rows of up to 128 nodes, up to
 // SPLIT_ROLE groups, z runs for about as many tiles as compute units.
 constexpr int SPLIT_TX_DEFAULT = 128;
-lbm_tile split_tile(int nx, int ny, int nz, int npt) {
+lbm_tile split_tile(int nx, int ny, int nz, int npt, int storage) {
     lbm_tile t{};
     t.tx = std::min(SPLIT_TX_DEFAULT, (nx + npt - 1) / npt * npt);
-    t.ty = std::max(1, std::min({ny, SPLIT_TY, split_rows(t.tx, npt)}));
+    t.ty = std::max(1, std::min({ny, SPLIT_TY, split_rows(t.tx, npt, storage)}));
     const int ncol = ((nx + t.tx - 1) / t.tx) * ((ny + t.ty - 1) / t.ty);
     const int nzc = std::max(1, (256 + ncol - 1) / ncol);
     t.cz = std::max(std::min(nz, 8), (nz + nzc - 1) / nzc);
@@ -394,6 +408,10 @@ template <class F> lbm_status dispatch(const lbm_ctx *c, F &&fn) {
     LBM_CASE(ST_F16S, OP_NONORTH, true)
     LBM_CASE(ST_F16S, OP_ORTH, false)
     LBM_CASE(ST_F16S, OP_ORTH, true)
+    LBM_CASE(ST_F16N, OP_NONORTH, false)
+    LBM_CASE(ST_F16N, OP_NONORTH, true)
+    LBM_CASE(ST_F16N, OP_ORTH, false)
+    LBM_CASE(ST_F16N, OP_ORTH, true)
 #undef LBM_CASE
     return fail(LBM_ERR_UNSUPPORTED, "no kernel for storage %d op %d wall %d", S, O, (int)W);
 }
@@ -421,7 +439,10 @@ lbm_status launch_step(lbm_ctx *c, const GridDesc &g, const void *src, void *dst
     return dispatch(c, [&](auto S, auto O, auto W) -> lbm_status {
         using T = typename Storage<S.value>::T;
         using R = typename Storage<S.value>::R;
-        if (box_walls(c->p)) {  // single phase with walls on x or y: own kernel
+        if constexpr (S.value == ST_F16N) {
+            // validate() admits F16N only where the split step runs.
+            if (c->mode != LBM_STEP_SPLIT) return fail(LBM_ERR_UNSUPPORTED, "F16N storage runs the split step only");
+        } else if (box_walls(c->p)) {  // single phase with walls on x or y: own kernel
             hipLaunchKernelGGL((k_single<S.value, O.value>), dim3(grid1d(g.N, 256, 1LL << 30)), dim3(256), 0,
                                c->stream, (const T *)src, (T *)dst, g, c->pd);
             HIP_TRY(hipGetLastError());
@@ -436,16 +457,25 @@ lbm_status launch_step(lbm_ctx *c, const GridDesc &g, const void *src, void *dst
             if constexpr (S.value != ST_F64) {
                 lbm_tile t{g.tx, g.ty, g.cz, 0};
                 if (g.nx % npt) return fail(LBM_ERR_INVALID_ARG, "split mode needs nx a multiple of %d", npt);
-                if (lbm_status e = check_split_tile(t, npt)) return e;
+                if (lbm_status e = check_split_tile(t, npt, S.value)) return e;
                 const bool r2 = split_ring2(g.tx, g.ty);
                 const bool nt = stream_stores(c->store_policy, 2 * (c->L.B - c->L.A));
 #define LBM_SPLIT_LAUNCH(R2, NT)                                                                              \
     hipLaunchKernelGGL((k_step_split<S.value, O.value, W.value, R2, NT>), dim3(grid), dim3(2 * SPLIT_ROLE), 0, \
                        c->stream, (const T *)src, (T *)dst, (const R *)c->gpsi(), g, c->pd)
-                if (r2 && nt) LBM_SPLIT_LAUNCH(true, true);
-                else if (r2) LBM_SPLIT_LAUNCH(true, false);
-                else if (nt) LBM_SPLIT_LAUNCH(false, true);
-                else LBM_SPLIT_LAUNCH(false, false);
+                if constexpr (S.value == ST_F16N) {
+                    // The pullers take the whole halo ring, in a second round
+                    // where it has more nodes than pullers: with the colliders
+                    // sharing it (RING2) the F16N step measured 43% slower
+                    // (0.474 against 0.332 ms at 256^3, 128 x 8 x 64 tiles).
+                    if (nt) LBM_SPLIT_LAUNCH(false, true);
+                    else LBM_SPLIT_LAUNCH(false, false);
+                } else {
+                    if (r2 && nt) LBM_SPLIT_LAUNCH(true, true);
+                    else if (r2) LBM_SPLIT_LAUNCH(true, false);
+                    else if (nt) LBM_SPLIT_LAUNCH(false, true);
+                    else LBM_SPLIT_LAUNCH(false, false);
+                }
 #undef LBM_SPLIT_LAUNCH
                 HIP_TRY(hipGetLastError());
                 return LBM_OK;
@@ -453,6 +483,9 @@ lbm_status launch_step(lbm_ctx *c, const GridDesc &g, const void *src, void *dst
                 return fail(LBM_ERR_UNSUPPORTED, "split mode needs FP32 or F16S storage");
             }
         }
+        if constexpr (S.value == ST_F16N) {
+            return LBM_OK;  // not reached: the split step returned above
+        } else {
         if (npt == 4) {
             if constexpr (S.value == ST_F16S) {
                 // nx and tx multiples of 4: checked by lbm_set_step_mode / lbm_set_tile
@@ -482,6 +515,7 @@ lbm_status launch_step(lbm_ctx *c, const GridDesc &g, const void *src, void *dst
                            c->stream, (const T *)src, (T *)dst, (const R *)c->gpsi(), g, c->pd);
         HIP_TRY(hipGetLastError());
         return LBM_OK;
+        }
     });
 }
 
@@ -489,6 +523,9 @@ lbm_status launch_slabs(lbm_ctx *c, const void *src, void *dst) {
     return dispatch(c, [&](auto S, auto O, auto W) -> lbm_status {
         using T = typename Storage<S.value>::T;
         using R = typename Storage<S.value>::R;
+        if constexpr (S.value == ST_F16N) {
+            return fail(LBM_ERR_UNSUPPORTED, "F16N storage runs the split step only");
+        } else {
         const int nz = c->p.nz;
         const long long plane = (long long)c->p.nx * c->p.ny;
         auto psi_pass = [&](int za, int zb) {
@@ -509,6 +546,7 @@ lbm_status launch_slabs(lbm_ctx *c, const void *src, void *dst) {
         }
         HIP_TRY(hipGetLastError());
         return LBM_OK;
+        }
     });
 }
 
@@ -531,7 +569,7 @@ lbm_status one_step(lbm_ctx *c) {
     lbm_status s = launch_walls(c, c->state());
     if (s) return s;
     if (c->write_check) {
-        const long long words = 19LL * c->g.N * (long long)elem_bytes(c->p.storage) / 2;
+        const long long words = (long long)pop_elems(c->p.storage) * c->g.N * (long long)elem_bytes(c->p.storage) / 2;
         hipLaunchKernelGGL(k_fill_ones, dim3(grid1d(words, 256)), dim3(256), 0, c->stream,
                            (uint16_t *)c->other(), words);
         HIP_TRY(hipGetLastError());
@@ -559,7 +597,7 @@ void default_mode(lbm_ctx *c) {
     const lbm_params &p = c->p;
     if (split_apply(p)) {
         c->mode = LBM_STEP_SPLIT;
-        c->tile = split_tile(p.nx, p.ny, p.nz, npt_of(LBM_STEP_SPLIT, p.storage));
+        c->tile = split_tile(p.nx, p.ny, p.nz, npt_of(LBM_STEP_SPLIT, p.storage), p.storage);
     } else if (pairs_apply(p)) {
         c->mode = LBM_STEP_PAIRS;
         c->tile = wide_tile(p.nx, p.ny, p.nz, 2);
@@ -904,7 +942,7 @@ lbm_status lbm_diagnostics(lbm_ctx *c, const lbm_diag_request *req, lbm_diag *ou
 
 lbm_status lbm_state_bytes(const lbm_ctx *c, size_t *bytes) {
     if (!c || !bytes) return fail(LBM_ERR_INVALID_ARG, "null argument");
-    *bytes = 19 * (size_t)c->g.N * elem_bytes(c->p.storage) + sizeof(int64_t);
+    *bytes = pop_elems(c->p.storage) * (size_t)c->g.N * elem_bytes(c->p.storage) + sizeof(int64_t);
     return LBM_OK;
 }
 
@@ -941,7 +979,8 @@ lbm_status lbm_load_state(lbm_ctx *c, const void *dev_buf, size_t bytes) {
 lbm_status lbm_set_tile(lbm_ctx *c, const lbm_tile *t) {
     if (!c || !t) return fail(LBM_ERR_INVALID_ARG, "null argument");
     const int npt = npt_of(c->mode, c->p.storage);
-    lbm_status s = c->mode == LBM_STEP_SPLIT ? check_split_tile(*t, npt) : check_tile(*t, c->p.storage, npt);
+    lbm_status s = c->mode == LBM_STEP_SPLIT ? check_split_tile(*t, npt, c->p.storage)
+                                             : check_tile(*t, c->p.storage, npt);
     if (s) return s;
     c->tile = *t;
     c->tile.reserved = 0;
@@ -971,7 +1010,9 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t trials, lbm_tile *best) {
         if (t.tx > c->p.nx && t.tx != std::min(c->p.nx, txmax)) return;
         if (t.ty > c->p.ny) return;
         if ((t.tx / npt) * t.ty < 64) return;
-        if ((c->mode == LBM_STEP_SPLIT ? check_split_tile(t, npt) : check_tile(t, c->p.storage, npt)) != LBM_OK) return;
+        if ((c->mode == LBM_STEP_SPLIT ? check_split_tile(t, npt, c->p.storage) : check_tile(t, c->p.storage, npt)) !=
+            LBM_OK)
+            return;
         for (auto &o : cand)
             if (o.tx == t.tx && o.ty == t.ty && o.cz == t.cz) return;
         cand.push_back(t);
@@ -980,7 +1021,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int32_t trials, lbm_tile *best) {
         for (int ty : tys)
             for (int cz : czs) add(std::min(tx, c->p.nx), ty, cz);
     if (cand.empty())
-        cand.push_back(c->mode == LBM_STEP_SPLIT ? split_tile(c->p.nx, c->p.ny, c->p.nz, npt)
+        cand.push_back(c->mode == LBM_STEP_SPLIT ? split_tile(c->p.nx, c->p.ny, c->p.nz, npt, c->p.storage)
                        : npt > 1           ? wide_tile(c->p.nx, c->p.ny, c->p.nz, npt)
                                            : default_tile(c->p.nx, c->p.ny, c->p.nz));
     g_err.clear();
@@ -1030,14 +1071,16 @@ lbm_status lbm_set_step_mode(lbm_ctx *c, int32_t mode, int32_t slab_planes) {
     if (mode == LBM_STEP_QUADS && !quads_apply(c->p))
         return fail(LBM_ERR_UNSUPPORTED, "quad mode needs F16S storage, nx a multiple of 4 (got %d) and no walls on x or y",
                     c->p.nx);
+    if (c->p.storage == ST_F16N && mode != LBM_STEP_SPLIT)
+        return fail(LBM_ERR_UNSUPPORTED, "F16N storage runs the split step only");
     if (mode == LBM_STEP_SPLIT && !split_apply(c->p))
-        return fail(LBM_ERR_UNSUPPORTED, "split mode needs F16S storage with nx a multiple of 4 or FP32 with even nx "
-                    "(got nx = %d), and no walls on x or y", c->p.nx);
+        return fail(LBM_ERR_UNSUPPORTED, "split mode needs F16S or F16N storage with nx a multiple of 4 or FP32 with "
+                    "even nx (got nx = %d), and no walls on x or y", c->p.nx);
     const int npt = npt_of(mode, c->p.storage);
     if (mode == LBM_STEP_SPLIT) {
-        if (check_split_tile(c->tile, npt) != LBM_OK) {
+        if (check_split_tile(c->tile, npt, c->p.storage) != LBM_OK) {
             g_err.clear();
-            c->tile = split_tile(c->p.nx, c->p.ny, c->p.nz, npt);
+            c->tile = split_tile(c->p.nx, c->p.ny, c->p.nz, npt, c->p.storage);
             fill_grid(c->g, c->p, c->tile);
         }
     } else if (check_tile(c->tile, c->p.storage, npt) != LBM_OK) {
@@ -1152,7 +1195,7 @@ lbm_tile batch_tile(const lbm_params &p, int item_nodes, int mode) {
     if (mode == LBM_STEP_SPLIT) {  // whole rows up to 128 nodes, as many rows as the LDS takes
         const int npt = npt_of(mode, p.storage);
         t.tx = std::min(SPLIT_TX_DEFAULT, p.nx);
-        t.ty = std::max(1, std::min(p.ny, split_rows(t.tx, npt)));
+        t.ty = std::max(1, std::min(p.ny, split_rows(t.tx, npt, p.storage)));
         const int cols = t.tx * t.ty;
         t.cz = std::max(1, std::min(p.nz, (item_nodes + cols / 2) / cols));
         return t;
@@ -1176,6 +1219,8 @@ lbm_status batch_validate(const lbm_params *runs, int32_t n) {
         if (s) return fail(s, "run %d: %s", k, g_err.c_str());
         if (runs[k].wall_z || runs[k].wall_x || runs[k].wall_y)
             return fail(LBM_ERR_UNSUPPORTED, "run %d: batched runs must be periodic", k);
+        if (runs[k].storage == LBM_STORE_F16N)
+            return fail(LBM_ERR_UNSUPPORTED, "run %d: batched runs take F64, F32 or F16S storage", k);
         if (runs[k].op != runs[0].op || runs[k].storage != runs[0].storage)
             return fail(LBM_ERR_INVALID_ARG, "run %d: all runs must share op and storage", k);
     }

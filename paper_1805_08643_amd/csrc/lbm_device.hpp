@@ -36,7 +36,10 @@ __host__ __device__ constexpr double wclass(int a) {
 }
 
 enum { OP_NONORTH = 0, OP_ORTH = 1 };
-enum { ST_F64 = 0, ST_F32 = 1, ST_F16S = 2 };
+enum { ST_F64 = 0, ST_F32 = 1, ST_F16S = 2, ST_F16N = 3 };
+// Direction planes of a population array: F16N adds a twentieth plane of
+// reference densities.
+__host__ __device__ constexpr int planes_of(int s) { return s == ST_F16N ? 20 : 19; }
 enum { PSI_SQRT_CS = 0, PSI_EXP = 1 };
 
 // ---------------------------------------------------------------------------
@@ -208,6 +211,27 @@ template <> struct Storage<ST_F16S> {
         __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(fmaf(v, hs, -shs))), r, (int)vo,
                                               (int)so, LBM_BUF_STORE_AUX);
     }
+};
+
+// binary16 relative to the pulling node: F16N stores every population that
+// arrives at node x as h_a = (fbar*_a - w_a rt(x)) * 2^e in binary16, where
+// rt(x) is the density of x at the step that wrote the state, itself rounded
+// to binary16 and kept in plane 19 at x.  Load and store are those of F16S;
+// only the shift (w_a rt(x) instead of w_a rho_ref) changes from node to node.
+template <> struct Storage<ST_F16N> : Storage<ST_F16S> {};
+
+// F16N reference density: binary16 bits of a density, and back.
+__device__ inline uint16_t nref_bits(float rho) { return __half_as_ushort(__float2half_rn(rho)); }
+__device__ inline float nref_val(uint16_t bits) { return __half2float(__ushort_as_half(bits)); }
+// Shifts w_a rt of the three velocity classes, one FP32 product each.
+struct NodeShift {
+    float s[3];
+    __device__ inline void set(float rt) {
+        s[0] = rt * (float)(1.0 / 3.0);
+        s[1] = rt * (float)(1.0 / 18.0);
+        s[2] = rt * (float)(1.0 / 36.0);
+    }
+    __device__ inline float operator()(int a) const { return a == 0 ? s[0] : (a <= 6 ? s[1] : s[2]); }
 };
 
 // Precision-explicit math (no silent promotion of float to double).  The

@@ -75,16 +75,17 @@ struct NbOff {
 };
 
 // Buffer descriptors over a population array: four groups of five direction
-// planes (the last group has four), so every offset within a group fits the
-// 32-bit scalar offset when 5 N sizeof(T) < 4 GiB.  Direction d lives in
-// group d / 5 at scalar offset (d % 5) * N sizeof(T) + plane offset.
+// planes (the last group has four, or five with the F16N reference plane), so
+// every offset within a group fits the 32-bit scalar offset when
+// 5 N sizeof(T) < 4 GiB.  Direction d lives in group d / 5 at scalar offset
+// (d % 5) * N sizeof(T) + plane offset.
 struct PopBuf {
     rsrc_t r[4];
     uint32_t dbytes;  // N * sizeof(T): bytes of one direction plane
-    template <class T> __device__ inline void set(const T *base, size_t N) {
+    template <class T> __device__ inline void set(const T *base, size_t N, int planes = Q) {
         dbytes = (uint32_t)(N * sizeof(T));
         for (int k = 0; k < 4; ++k) {
-            const int nd = k < 3 ? 5 : 4;
+            const int nd = k < 3 ? 5 : planes - 15;
             r[k] = make_rsrc(base + (size_t)(5 * k) * N, (uint32_t)nd * dbytes);
         }
     }
@@ -105,7 +106,17 @@ __device__ inline void pull(const PopBuf &A, int nz, uint32_t PB, int z, const N
     const int zm = WALL ? (bot ? z : z - 1) : (z == 0 ? nz - 1 : z - 1);
     const int zq = WALL ? (top ? z : z + 1) : (z == nz - 1 ? 0 : z + 1);
     const uint32_t pc = (uint32_t)z * PB, pm = (uint32_t)zm * PB, pq = (uint32_t)zq * PB;
-#define LBM_LD(d, plane, off) ST::ldb(A.of(d), (off), A.so((d), (plane)), P.sh(d), P.hsi)
+    // F16N: every population arriving here is stored against this node's
+    // reference density (plane 19 at the node).
+    NodeShift ns;
+    if constexpr (S == ST_F16N)
+        ns.set(nref_val((uint16_t)__builtin_amdgcn_raw_buffer_load_b16(A.of(19), (int)o.c, (int)A.so(19, pc),
+                                                                          LBM_BUF_AUX)));
+    auto sh = [&](int d) {
+        if constexpr (S == ST_F16N) return ns(d);
+        else return P.sh(d);
+    };
+#define LBM_LD(d, plane, off) ST::ldb(A.of(d), (off), A.so((d), (plane)), sh(d), P.hsi)
     f[0] = LBM_LD(0, pc, o.c);
     f[1] = LBM_LD(1, pc, o.xm);
     f[2] = LBM_LD(2, pc, o.xp);
@@ -172,13 +183,16 @@ template <int S>
 __device__ inline void pull_box(const typename Storage<S>::T *__restrict__ A, const GridDesc &g, int x, int y,
                                 int z, const Phys<typename Storage<S>::R> &P, typename Storage<S>::R f[Q]) {
     using ST = Storage<S>;
+    NodeShift ns;
+    if constexpr (S == ST_F16N) ns.set(nref_val(A[(size_t)19 * g.N + ((size_t)z * g.ny + y) * g.nx + x]));
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
         size_t idx;
         int d;
         bool lid;
         box_source(g, x, y, z, a, idx, d, lid);
-        f[a] = ST::load(A + (size_t)d * g.N + idx, P.sh(a), P.hsi);
+        const typename Storage<S>::R sh = S == ST_F16N ? (typename Storage<S>::R)ns(a) : P.sh(a);
+        f[a] = ST::load(A + (size_t)d * g.N + idx, sh, P.hsi);
         if (lid) f[a] += lid_term(P, a);
     }
 }
@@ -195,7 +209,7 @@ __device__ inline void pull_at(const typename Storage<S>::T *__restrict__ A, con
     o.set(x, wrapi(x - 1, g.nx), wrapi(x + 1, g.nx), y, wrapi(y - 1, g.ny), wrapi(y + 1, g.ny), g.nx,
           (uint32_t)sizeof(typename Storage<S>::T));
     PopBuf pb;
-    pb.set(A, (size_t)g.N);
+    pb.set(A, (size_t)g.N, planes_of(S));
     pull<S, WALL>(pb, g.nz, (uint32_t)((size_t)g.nx * g.ny * sizeof(typename Storage<S>::T)), z, o, P, f);
 }
 
@@ -755,6 +769,7 @@ template <> struct Lane8<ST_F16S> {
         return fmaf(__half2float(__ushort_as_half((uint16_t)(w >> (16 * k)))), hsi, shift);
     }
 };
+template <> struct Lane8<ST_F16N> : Lane8<ST_F16S> {};
 template <> struct Lane8<ST_F32> {
     static constexpr int NPT = 2, BITS = 32;
     using B = uint32_t;
@@ -789,6 +804,16 @@ template <> struct Out8<ST_F16S> {
     __device__ inline unsigned long long word(int a) const {
         return (unsigned long long)__builtin_bit_cast(uint32_t, lo[a]) |
                ((unsigned long long)__builtin_bit_cast(uint32_t, hi[a]) << 32);
+    }
+};
+// F16N: the shift of each value is that of the node it is stored for.
+template <> struct Out8<ST_F16N> : Out8<ST_F16S> {
+    __device__ inline void put_sh(int k, int a, float v, float shh, float hs) {
+        const _Float16 h = (_Float16)fmaf(v, hs, -shh);
+        if (k == 0) lo[a].x = h;
+        else if (k == 1) lo[a].y = h;
+        else if (k == 2) hi[a].x = h;
+        else hi[a].y = h;
     }
 };
 template <> struct Out8<ST_F32> {
@@ -935,6 +960,14 @@ __device__ inline void fold8(Wide8 &r, const Seam8<S> &sm, int nz, int z, bool w
 template <int S> __device__ inline void unpack8(const Wide8 &r, int k, const Phys<float> &P, float f[Q]) {
 #pragma unroll
     for (int a = 0; a < Q; ++a) f[a] = Lane8<S>::cvt(r.w[a], k, P.sh(a), P.hsi);
+}
+// F16N: node k's populations against its reference density, element k of
+// the group's reference word rw (plane 19 at the group).
+__device__ inline void unpack8n(const Wide8 &r, unsigned long long rw, int k, const Phys<float> &P, float f[Q]) {
+    NodeShift ns;
+    ns.set(nref_val((uint16_t)(rw >> (16 * k))));
+#pragma unroll
+    for (int a = 0; a < Q; ++a) f[a] = Lane8<ST_F16N>::cvt(r.w[a], k, ns(a), P.hsi);
 }
 
 // z-march of a tile with four nodes per thread: tx nodes (a multiple of 4)
@@ -1107,24 +1140,39 @@ constexpr int SPLIT_TX = 256, SPLIT_TY = 8, SPLIT_ROLE = 256;  // max tile width
 constexpr int SPLIT_SP = 6 * (SPLIT_TX + 2);                    // psi ring slot: (tx + 2)(ty + 2) <= 256 x 4 + ring
 constexpr int SPLIT_NODES = 1024;                               // max nodes per tile plane
 
-struct SplitLds {
+template <int S> struct SplitLds {
     unsigned long long qbuf[3][Q][SPLIT_ROLE];  // populations of three planes, one group per slot
     float rbuf[3][SPLIT_NODES];                 // densities of three planes
     float ring[4][SPLIT_SP];                    // psi ring
 };
+// F16N adds a ring of this step's binary16 densities (with the halo): the
+// references of the populations the colliders store, each for the node that
+// will pull it.  To stay within the 160 KiB of LDS its tiles are smaller,
+// (tx + 2)(ty + 2) <= 1300 (128 x 8 nodes at most), and the colliders load
+// the reference word of their own group (the references of the populations
+// in qbuf) from HBM, where the pullers read it two planes earlier: 160,224 bytes.
+constexpr int SPLIT_SP_N = 1300;
+template <> struct SplitLds<ST_F16N> {
+    unsigned long long qbuf[3][Q][SPLIT_ROLE];
+    float rbuf[3][SPLIT_NODES];
+    float ring[4][SPLIT_SP_N];
+    uint16_t nring[4][SPLIT_SP_N];  // binary16 densities of this step, slots as the psi ring
+};
 
 // One tile of the split step; every thread of the 512-thread block calls it.
-// RING2: the tile's halo ring has more nodes than there are pulling threads.
+// RING2: the tile's halo ring has more nodes than there are pulling threads,
+// and the colliders take the rest (without RING2 the pullers take a ring of
+// up to 2 SPLIT_ROLE nodes in two rounds; F16N always runs that way).
 // NT: the populations are stored with the non-temporal cache policy.
 template <int S, int OP, bool WALL, bool RING2, bool NT>
 __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, typename Storage<S>::T *__restrict__ B,
                                   const float *__restrict__ gpsi, const GridDesc &g, const Phys<float> &P, int tile,
-                                  SplitLds &L) {
+                                  SplitLds<S> &L) {
     using R = float;
     using T = typename Storage<S>::T;
     constexpr int NPT = Lane8<S>::NPT;
+    constexpr bool NREF = S == ST_F16N;
     auto &qbuf = L.qbuf;
-    auto &rbuf = L.rbuf;
     auto &ring = L.ring;
     const int TX = g.tx, TY = g.ty, TXG = g.tx / NPT;
     const int SX = TX + 2;
@@ -1157,10 +1205,11 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
     constexpr uint32_t E = sizeof(T);
     const uint32_t PB = (uint32_t)((size_t)nx * ny * E);
     PopBuf bA, bB;
-    bA.set(A, N);
-    bB.set(B, N);
+    bA.set(A, N, planes_of(S));
+    bB.set(B, N, planes_of(S));
+    // Offsets and halo nodes are set up inside each role's branch (setup
+    // below), so that neither role's loop carries the other's registers.
     NbOff8<S> oin;
-    oin.set(gx, wl, wr, gy, wrapi(gy - 1, ny), wrapi(gy + 1, ny), nx);
 
     // Halo ring: nh <= (1 + CR) SPLIT_ROLE nodes.  Each puller takes node rid
     // and, without RING2 (nh <= SPLIT_ROLE), node rid + SPLIT_ROLE in a second
@@ -1172,17 +1221,19 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
     // FP32 1% faster and F16S 3% slower even where it is not taken), and
     // without RING2 the colliders' loop carries no halo code at all.
     constexpr int HR = RING2 ? 1 : 2;                // halo rounds of a puller
-    constexpr int CR = S == ST_F16S ? 1 : 2;         // halo rounds of a collider (RING2)
+    constexpr int CR = NPT == 4 ? 1 : 2;             // halo rounds of a collider (RING2)
     const int nh = 2 * SX + 2 * TY;
     int chl[2], hxs[2], hys[2];
     bool halo[2];
     NbOff oh[2];
+    auto setup = [&](const bool pull_role) {
+    oin.set(gx, wl, wr, gy, wrapi(gy - 1, ny), wrapi(gy + 1, ny), nx);
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-        const int h = puller ? rid + r * SPLIT_ROLE : rid + (r + 1) * SPLIT_ROLE;
+        const int h = pull_role ? rid + r * SPLIT_ROLE : rid + (r + 1) * SPLIT_ROLE;
         int hlx = -1, hly = -1;
         halo[r] = false;
-        if ((puller ? r < HR : RING2 && r < CR) && h < nh) {
+        if ((pull_role ? r < HR : RING2 && r < CR) && h < nh) {
             if (h < SX) {
                 hlx = h - 1;
                 hly = -1;
@@ -1204,11 +1255,16 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
         oh[r].set(hxs[r], wrapi(hxs[r] - 1, nx), wrapi(hxs[r] + 1, nx), hys[r], wrapi(hys[r] - 1, ny),
                   wrapi(hys[r] + 1, ny), nx, E);
     }
+    };
     // Colliding waves with a halo node in the first / second round (wave-uniform).
     const bool chw = RING2 && !puller && (int)__builtin_amdgcn_readfirstlane(rid) + SPLIT_ROLE < nh;
     const bool chw2 = RING2 && CR > 1 && !puller && (int)__builtin_amdgcn_readfirstlane(rid) + 2 * SPLIT_ROLE < nh;
     auto zwrap = [&](int zp) { return WALL ? zp : wrapi(zp, nz); };
     auto rslot = [&](int z) { return ring[(z - zb + 1) & 3]; };
+    auto nslot = [&](int z) -> uint16_t * {
+        if constexpr (NREF) return L.nring[(z - zb + 1) & 3];
+        else return nullptr;
+    };
     auto bslot = [&](int z) { return (z - zb + 3) % 3; };
 
     // Puller: plane p into the LDS buffers.  (Keeping the next plane's loads
@@ -1231,13 +1287,23 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
         Wide8 q;
         Seam8<S> sm;
         load8<S, WALL>(bA, nz, PB, pw, oin, q, sm);
+        unsigned long long rw = 0;  // F16N: reference densities of the group's nodes
+        if constexpr (NREF)
+            rw = __builtin_bit_cast(unsigned long long,
+                                    __builtin_amdgcn_raw_buffer_load_b64(
+                                        bA.of(19), (int)oin.c,
+                                        (int)u_so(bA, 19, __builtin_amdgcn_readfirstlane((uint32_t)pw * PB)),
+                                        LBM_BUF_AUX));
+        uint16_t *nsl = nslot(p);
         // The halo node's loads are consumed in the branch that issued them.
 #pragma unroll
         for (int r = 0; r < HR; ++r) {
             if (halo[r]) {
                 R fh[Q];
                 pull<S, WALL>(bA, nz, PB, pw, oh[r], P, fh);
-                slot[chl[r]] = pseudo_psi<R>(P, sum19<R>(fh));
+                const R rh = sum19<R>(fh);
+                slot[chl[r]] = pseudo_psi<R>(P, rh);
+                if constexpr (NREF) nsl[chl[r]] = nref_bits(rh);
             }
         }
         fold8<S, WALL>(q, sm, nz, pw, wl, wr);
@@ -1249,11 +1315,15 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             R f[Q];
-            unpack8<S>(q, k, P, f);
+            if constexpr (NREF) unpack8n(q, rw, k, P, f);
+            else unpack8<S>(q, k, P, f);
             const R rho = sum19<R>(f);
             const R psi = pseudo_psi<R>(P, rho);
-            if (need_in) slot[cin + k] = psi;
-            if (active) rbuf[bs][nb + k] = rho;
+            if (need_in) {
+                slot[cin + k] = psi;
+                if constexpr (NREF) nsl[cin + k] = nref_bits(rho);
+            }
+            if (active) L.rbuf[bs][nb + k] = rho;
         }
     };
     // Collider's share of the halo ring of plane p (RING2), round r.
@@ -1266,37 +1336,73 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
         }
         R fh[Q];
         pull<S, WALL>(bA, nz, PB, zwrap(p), oh[r], P, fh);
-        const R psh = pseudo_psi<R>(P, sum19<R>(fh));
-        if (halo[r]) slot[chl[r]] = psh;
+        const R rh = sum19<R>(fh);
+        const R psh = pseudo_psi<R>(P, rh);
+        if (halo[r]) {
+            slot[chl[r]] = psh;
+            if constexpr (NREF) nslot(p)[chl[r]] = nref_bits(rh);
+        }
     };
-    // Collider: plane c from the LDS buffers to B.
-    auto collide_plane = [&](int c) {
+    // F16N: reference word of the group at plane c in A (the colliders'
+    // copy of what the pullers read).
+    auto ref_word = [&](int c) -> unsigned long long {
+        return __builtin_bit_cast(unsigned long long,
+                                  __builtin_amdgcn_raw_buffer_load_b64(
+                                      bA.of(19), (int)oin.c,
+                                      (int)u_so(bA, 19, __builtin_amdgcn_readfirstlane((uint32_t)c * PB)),
+                                      LBM_BUF_AUX));
+    };
+    // Collider: plane c from the LDS buffers to B (rw: F16N reference word).
+    auto collide_plane = [&](int c, unsigned long long rw) {
         if (!active) return;
         const int bs = bslot(c);
         Wide8 q;
 #pragma unroll
         for (int a = 0; a < Q; ++a) q.w[a] = qbuf[bs][a][rid];
         const R *lo = rslot(c - 1), *mid = rslot(c), *hi = rslot(c + 1);
+        // F16N: this step's references of the planes below, at and above
+        // (a population leaving through a wall comes back to its own node).
+        const uint16_t *nlo = nslot(c - 1), *nmid = nslot(c), *nhi = nslot(c + 1);
+        const bool bot = WALL && c == 0, top = WALL && c == nz - 1;
         Out8<S> out;
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             R f[Q];
-            unpack8<S>(q, k, P, f);
+            if constexpr (NREF) unpack8n(q, rw, k, P, f);
+            else unpack8<S>(q, k, P, f);
             R ax, ay, az;
             psi_stencil<R>(lo, mid, hi, cin + k, SX, ax, ay, az);
-            const R rho = rbuf[bs][nb + k];
+            const R rho = L.rbuf[bs][nb + k];
             const R mG_psi = -P.G * mid[cin + k];
             collide<R, OP>(f, rho, mG_psi * ax + rho * P.gx, mG_psi * ay + rho * P.gy, mG_psi * az + rho * P.gz,
                            ax * ax + ay * ay + az * az, P);
+            if constexpr (NREF) {
 #pragma unroll
-            for (int a = 0; a < Q; ++a) out.put(k, a, f[a], P);
+                for (int a = 0; a < Q; ++a) {
+                    const bool back = (ez(a) < 0 && bot) || (ez(a) > 0 && top);
+                    const uint16_t *pl = back ? nmid : (ez(a) < 0 ? nlo : (ez(a) > 0 ? nhi : nmid));
+                    const int pos = back ? cin + k : cin + k + ex(a) + ey(a) * SX;
+                    const R sh = nref_val(pl[pos]) * (R)wclass(a);
+                    out.put_sh(k, a, f[a], sh * P.hs, P.hs);
+                }
+            } else {
+#pragma unroll
+                for (int a = 0; a < Q; ++a) out.put(k, a, f[a], P);
+            }
         }
         const uint32_t pz = __builtin_amdgcn_readfirstlane((uint32_t)c * PB);
+        using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(bB.of(0), 0, 0, 0));
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
-            using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(bB.of(a), 0, 0, 0));
             __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, out.word(a)), bB.of(a), (int)oin.c,
                                                   (int)u_so(bB, a, pz), NT ? LBM_BUF_NT : LBM_BUF_STORE_AUX);
+        }
+        if constexpr (NREF) {  // the group's own references, for the next step's pull
+            unsigned long long ro = 0;
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) ro |= (unsigned long long)nmid[cin + k] << (16 * k);
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, ro), bB.of(19), (int)oin.c,
+                                                  (int)u_so(bB, 19, pz), NT ? LBM_BUF_NT : LBM_BUF_STORE_AUX);
         }
     };
 
@@ -1307,15 +1413,24 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
     // iterations) that meet at the same number of barriers.
     const int iters = (ze - zb) + 3;
     if (puller) {
+        setup(true);
         for (int i = 0; i < iters; ++i) {
             const int p = zb - 1 + i;
             if (p <= ze) pull_plane(p);
             lds_barrier();
         }
     } else {
+        setup(false);
+        unsigned long long rw_next = 0;
         for (int i = 0; i < iters; ++i) {
             const int c = zb - 3 + i;
-            if (c >= zb) collide_plane(c);
+            // F16N: the next plane's reference word, issued a plane ahead and
+            // before this plane's stores.
+            const unsigned long long rw = rw_next;
+            if constexpr (NREF) {
+                if (c + 1 >= zb && c + 1 < ze) rw_next = ref_word(c + 1);
+            }
+            if (c >= zb) collide_plane(c, rw);
             if constexpr (RING2) {
                 if (chw && c + 2 <= ze) halo_plane(c + 2, 0);
                 if constexpr (CR > 1) {
@@ -1331,7 +1446,7 @@ template <int S, int OP, bool WALL, bool RING2, bool NT>
 __global__ void __launch_bounds__(2 * SPLIT_ROLE)
     k_step_split(const typename Storage<S>::T *__restrict__ A, typename Storage<S>::T *__restrict__ B,
                  const float *__restrict__ gpsi, GridDesc g, PhysD pd) {
-    __shared__ SplitLds lds;
+    __shared__ SplitLds<S> lds;
     const int tile = xcd_tile(blockIdx.x, g.per_xcd);
     if (tile >= g.ntiles) return;
     Phys<float> P;
@@ -1420,7 +1535,7 @@ __global__ void __launch_bounds__(2 * SPLIT_ROLE)
     k_batch_split(unsigned char *__restrict__ ws, const RunDesc *__restrict__ runs, int nruns, int total_tiles,
                   int parity) {
     using T = typename Storage<S>::T;
-    __shared__ SplitLds lds;
+    __shared__ SplitLds<S> lds;
     const int per_xcd = (total_tiles + 7) / 8;
     const int nvirt = 8 * per_xcd;
     for (int v = blockIdx.x; v < nvirt; v += gridDim.x) {
@@ -1679,6 +1794,19 @@ __device__ inline void scatter_node(typename Storage<S>::T *__restrict__ A, cons
                                     const Phys<typename Storage<S>::R> &P, int x, int y, int z,
                                     const typename Storage<S>::R v[Q]) {
     using ST = Storage<S>;
+    using R = typename ST::R;
+    // F16N: the node's own density, rounded to binary16, is the reference of
+    // every population that arrives here; it goes to plane 19 at the node.
+    NodeShift ns;
+    if constexpr (S == ST_F16N) {
+        const uint16_t rt = nref_bits(sum19<R>(v));
+        A[(size_t)19 * g.N + ((size_t)z * g.ny + y) * g.nx + x] = rt;
+        ns.set(nref_val(rt));
+    }
+    auto shh = [&](int a) -> R {
+        if constexpr (S == ST_F16N) return ns(a) * P.hs;
+        else return P.shh(a);
+    };
     if (g.wall_x | g.wall_y) {
 #pragma unroll
         for (int a = 0; a < Q; ++a) {
@@ -1686,7 +1814,7 @@ __device__ inline void scatter_node(typename Storage<S>::T *__restrict__ A, cons
             int d;
             bool lid;
             box_source(g, x, y, z, a, idx, d, lid);
-            ST::store(A + (size_t)d * g.N + idx, lid ? v[a] - lid_term(P, a) : v[a], P.shh(d), P.hs);
+            ST::store(A + (size_t)d * g.N + idx, lid ? v[a] - lid_term(P, a) : v[a], shh(d), P.hs);
         }
         return;
     }
@@ -1702,7 +1830,7 @@ __device__ inline void scatter_node(typename Storage<S>::T *__restrict__ A, cons
             sz = wrapi(sz, g.nz);
             idx = ((size_t)sz * g.ny + wrapi(y - ey(a), g.ny)) * g.nx + wrapi(x - ex(a), g.nx);
         }
-        ST::store(A + (size_t)d * g.N + idx, v[a], P.shh(a), P.hs);
+        ST::store(A + (size_t)d * g.N + idx, v[a], shh(a), P.hs);
     }
 }
 

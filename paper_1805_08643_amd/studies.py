@@ -630,11 +630,13 @@ def laplace_cs(ops=("nonorth", "orth"), storages=("f64", "f32"), radii=(24, 28, 
 
 
 def precision(steps=(100, 500, 1000, 2000), n=256, crop=64):
-    """Density error of FP32 and shifted-FP16 storage against FP64 storage on
-    the central crop^3 box, the droplet-pair observables, and the relative
-    mass drift of each run.  Shifted FP16 runs with the default shift
+    """Density error of FP32 and 16-bit storage against FP64 storage on the
+    central crop^3 box, the droplet-pair observables, and the relative mass
+    drift of each run.  Shifted FP16 runs with the default shift
     rho_ref = rho_V ("f16s") and the two control shifts, rho_ref = 0
-    ("f16s_rho0", unshifted) and rho_ref = (rho_L + rho_V) / 2 ("f16s_mid")."""
+    ("f16s_rho0", unshifted) and rho_ref = (rho_L + rho_V) / 2 ("f16s_mid");
+    "f16n" shifts every population by the binary16 density of the node that
+    pulls it."""
     import torch
 
     import lbm_inputs as li
@@ -643,7 +645,7 @@ def precision(steps=(100, 500, 1000, 2000), n=256, crop=64):
         steps = (steps,)
     cfg, init = li.c3_two_droplets(n=n)
     shifts = {"f16s": init["rho_V"], "f16s_rho0": 0.0, "f16s_mid": 0.5 * (init["rho_L"] + init["rho_V"])}
-    variants = ("f32", "f16s", "f16s_rho0", "f16s_mid")
+    variants = ("f32", "f16s", "f16s_rho0", "f16s_mid", "f16n")
     lats = {}
     for st in ("f64",) + variants:
         c = dict(cfg, storage="f16s" if st.startswith("f16s") else st, rho_ref=shifts.get(st, init["rho_V"]),

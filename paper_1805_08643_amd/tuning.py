@@ -23,6 +23,7 @@ STEP_TILES = {
     ("two_droplets_256", "f16s", "pairs"): (128, 8, 64),
     ("two_droplets_256", "f16s", "quads"): (128, 16, 32),
     ("two_droplets_256", "f16s", "split"): (128, 8, 64),
+    ("two_droplets_256", "f16n", "split"): (128, 8, 64),
     ("sessile_384x384x192", "f32", "fused"): (64, 4, 32),
     ("sessile_384x384x192", "f32", "pairs"): (128, 8, 16),
     ("sessile_384x384x192", "f32", "split"): (128, 4, 48),
@@ -39,6 +40,8 @@ STEP_MODES = {
 
 
 def mode_for(workload: str, storage: str) -> str:
+    if storage == "f16n":  # the split step is F16N's only kernel
+        return "split"
     return STEP_MODES.get((workload, storage), "fused")
 
 

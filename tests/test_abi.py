@@ -138,7 +138,33 @@ def test_make_params_mapping():
     assert p.s_nu == 1.25 and p.s_eps == 1.4 and p.s_m == 1.2 and p.gravity[2] == -1e-6
 
 
-@pytest.mark.parametrize("storage,nz_max", [("f64", 262), ("f32", 524), ("f16s", 1048)])
+def test_f16n_layout_and_limits():
+    """F16N holds a twentieth plane (the reference densities) beside the 19
+    populations of 2 bytes, and runs the split step only: nx a multiple of 4,
+    walls only on z, no batches."""
+    p = binding.lbm_params_default()
+    p.storage = binding.STORAGE["f16s"]
+    n16s = binding.lbm_workspace_bytes(p)
+    p.storage = binding.STORAGE["f16n"]
+    n16n = binding.lbm_workspace_bytes(p)
+    assert n16n - n16s == 2 * 32 ** 3 * 2  # one more plane of 2-byte values in each of the two buffers
+    n = ctypes.c_size_t(0)
+    L = binding.lib()
+    p.nx = 30
+    assert L.lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == -5
+    assert "F16N" in binding.lbm_last_error()
+    p.nx = 32
+    p.wall_z = 1
+    assert L.lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == 0
+    p.wall_z, p.wall_x = 0, 1
+    assert L.lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == -5
+    p.wall_x = 0
+    arr = (binding.LbmParams * 2)(p, p)
+    assert L.lbm_batch_workspace_bytes(arr, 2, ctypes.byref(n)) == -5
+    assert binding.algorithmic_bytes_per_node("f16n") == 80
+
+
+@pytest.mark.parametrize("storage,nz_max", [("f64", 262), ("f32", 524), ("f16s", 1048), ("f16n", 1048)])
 def test_largest_lattice_accepted_next_rejected(storage, nz_max):
     """Five direction planes must fit the 32-bit buffer offsets (< 4 GiB):
     640 x 640 x nz_max is the largest such lattice, one plane more is not."""

@@ -1,0 +1,276 @@
+"""GPU parity of the node-referenced binary16 storage (F16N).
+
+F16N stores every population that node x will pull as binary16 of
+(fbar_a - w_a rt(x)) 2^e, where rt(x) is the density of x at the step that
+wrote the state, rounded to binary16 and kept in a twentieth plane.  As for
+F16S (``test_gpu_f16s``), two sources of difference separate an F16N run
+from the FP64 oracle: the storage rounding, and the FP32 arithmetic.  The
+oracle measures the first through the host emulation of the format
+(``round_trip_n``: after every FP64 step, the state rounded against the
+densities of the state before it).  The tests check:
+
+* writing and reading back populations through the C ABI equals the format
+  exactly, with the references the library stored;
+* one step from the same stored state: the library's references are the
+  binary16 densities of the oracle's state (one unit apart where the FP32
+  density lies at a rounding midpoint), and its stored populations are the
+  format applied to the oracle's collision, each against the stored
+  reference of the node that will pull it (a population leaving through a
+  wall against its own node's), up to the FP32 arithmetic;
+* several steps: within twice the emulated format's own error over the
+  node's 5^3 neighbourhood, plus half a binary16 unit of the largest stored
+  value there, plus the FP32 bound;
+* precision: on the two-droplet collision, the density error of F16N
+  against FP64 storage is several times below that of F16S, and within
+  2e-3 (liquid) and 5e-3 (vapour) over 400 steps.
+"""
+import numpy as np
+import pytest
+import torch
+from scipy.ndimage import maximum_filter
+
+import lbm_inputs as li
+from oracle import moments, ref
+from paper_1805_08643_amd.binding import Lattice, f16_exp_for
+from tests import f16s_format as fmt
+from tests.test_gpu_f16s import _check_one_step
+
+pytestmark = pytest.mark.gpu
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _near_max(field, cfg, size=5):
+    a = field.reshape(cfg["nz"], cfg["ny"], cfg["nx"])
+    mode = ("nearest" if cfg.get("wall_z", 0) else "wrap", "wrap", "wrap")
+    return maximum_filter(a, size=size, mode=mode).reshape(-1)
+
+
+def _moved(init, dx, dy, dz):
+    return dict(init, droplets=[dict(d, center=(d["center"][0] + dx, d["center"][1] + dy, d["center"][2] + dz))
+                                for d in init["droplets"]])
+
+
+CASES = {
+    "droplet_32": lambda: li.c1_droplet(),
+    "ragged_68x37x21": lambda: (dict(li.c3_two_droplets(n=64)[0], nx=68, ny=37, nz=21),
+                                _moved(li.c3_two_droplets(n=64)[1], 3, -14, -22)),
+    "walls_40x33x19_60deg": lambda: li.c4_sessile(60.0, nx=40, ny=33, nz=19, r0=8.0),
+    # rows of 128 nodes: a halo ring of 276 nodes, more than the 256 pullers (their second round)
+    "wide_128x20x10": lambda: (dict(li.c3_two_droplets(n=64)[0], nx=128, ny=20, nz=10),
+                               _moved(li.c3_two_droplets(n=64)[1], 32, -22, -27)),
+}
+TILES = {"wide_128x20x10": (128, 8, 5)}
+
+
+def _case(name, op="nonorth"):
+    cfg, init = CASES[name]()
+    cfg = dict(cfg, op=op, storage="f16n", f16_exp=f16_exp_for(1.25 * init["rho_L"]))
+    rho, u = li.init_fields(cfg, init)
+    p = ref.make_params(cfg)
+    return cfg, init, p, ref.equilibrium(p, rho, u)
+
+
+def _raw(lat, cfg):
+    """(h, rt): the stored binary16 populations (19, N) and references (N)."""
+    N = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    raw = lat.save_state()[:20 * N * 2].view(torch.int16).reshape(20, N).cpu().numpy().view(np.float16)
+    return raw[:19], raw[19]
+
+
+def _puller(cfg):
+    """(19, N) index of the node that pulls the value stored at (a, x'):
+    x' + e_a (periodic), or x' itself where that lies beyond a wall."""
+    nx, ny, nz = cfg["nx"], cfg["ny"], cfg["nz"]
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    own = (z * ny + y) * nx + x
+    out = np.empty((19, nx * ny * nz), dtype=np.int64)
+    for a, (ex, ey, ez) in enumerate(moments.VELOCITIES):
+        zz = z + ez
+        beyond = ((zz < 0) | (zz >= nz)) if cfg.get("wall_z", 0) else np.zeros_like(zz, dtype=bool)
+        d = ((zz % nz) * ny + (y + ey) % ny) * nx + (x + ex) % nx
+        out[a] = np.where(beyond, own, d).reshape(-1)
+    return out
+
+
+def _pulled(h, cfg):
+    """Stored values (19, N) in the order of the nodes that pull them:
+    element (a, x) is what x pulls in direction a, h[a][x - e_a], or
+    h[opp(a)][x] where x - e_a lies beyond a wall."""
+    nx, ny, nz = cfg["nx"], cfg["ny"], cfg["nz"]
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    own = ((z * ny + y) * nx + x).reshape(-1)
+    out = np.empty_like(h)
+    for a, (ex, ey, ez) in enumerate(moments.VELOCITIES):
+        zz = z - ez
+        beyond = (((zz < 0) | (zz >= nz)) if cfg.get("wall_z", 0) else np.zeros_like(zz, dtype=bool)).reshape(-1)
+        s = (((zz % nz) * ny + (y - ey) % ny) * nx + (x - ex) % nx).reshape(-1)
+        out[a] = np.where(beyond, h[moments.opposite(a)][own], h[a][s])
+    return out
+
+
+def _lattice(cfg, f0, mode=None, tile=None):
+    _need_gpu()
+    print(f"[gpu] f16n {cfg['nx']}x{cfg['ny']}x{cfg['nz']} wall={cfg.get('wall_z', 0)} op={cfg['op']} "
+          f"tile={tile}", flush=True)
+    lat = Lattice(cfg)
+    if mode is not None:
+        lat.set_step_mode(mode)
+    if tile is not None:
+        lat.set_tile(*tile)
+    lat.write_populations(f0)
+    return lat
+
+
+def _ref_units(got, want):
+    return np.abs(fmt.ordered_bits(got) - fmt.ordered_bits(want))
+
+
+def test_f16n_write_read_round_trip():
+    """Written populations read back as the format with the references the
+    library stored; those references are the binary16 densities of the
+    written populations (a unit apart only where the FP32 sum lies at a
+    rounding midpoint)."""
+    cfg, init, p, f0 = _case("droplet_32")
+    f = f0 * (1 + 0.05 * li.random_populations(32, 32, 32, 9, -1, 1))
+    lat = _lattice(cfg, f)
+    h, rt = _raw(lat, cfg)
+    got = lat.read_populations().cpu().numpy()
+    lat.close()
+    u = _ref_units(rt, fmt.ref_bits(f.sum(0)))
+    print(f"  references a unit off: {float((u != 0).mean()):.2e}")
+    assert u.max() <= 1 and (u != 0).mean() < 1e-3
+    h_pulled = _pulled(h, cfg)
+    assert np.array_equal(h_pulled, fmt.encode_n(f, rt, cfg))
+    assert np.array_equal(got, fmt.decode_n(h_pulled, rt, cfg))
+
+
+@pytest.mark.parametrize("op", ["nonorth", "orth"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_f16n_one_step_equals_format_emulation(name, op):
+    cfg, init, p, f0 = _case(name, op)
+    lat = _lattice(cfg, f0, tile=TILES.get(name))
+    h0, rt0 = _raw(lat, cfg)
+    lat.step(1)
+    h1, rt1 = _raw(lat, cfg)
+    lat.close()
+    f_in = fmt.decode_n(_pulled(h0, cfg), rt0, cfg)  # the state the library stepped
+    N = f_in.shape[1]
+    w64 = ref.collide_nodes(p, f_in, np.arange(N)).T
+    u = _ref_units(rt1, fmt.ref_bits(f_in.sum(0)))
+    print(f"  references a unit off: {float((u != 0).mean()):.2e}")
+    assert u.max() <= 1 and (u != 0).mean() < 1e-2
+    want = fmt.encode_n(w64, rt1[_puller(cfg)], cfg)
+    _check_one_step(h1, want, w64.sum(0)[None, :], cfg)
+
+
+def _o16n_and_exact(p, cfg, f0, checkpoints):
+    """(emulated-format oracle states, the largest |stored value| each held,
+    plain FP64 oracle states)."""
+    o16, hm, ex = [], [], []
+    f16 = fmt.round_trip_n(f0, f0.sum(0), cfg)
+    f64 = f0
+    done = 0
+    for s in checkpoints:
+        for _ in range(s - done):
+            prev = f16.sum(0)
+            f16 = fmt.round_trip_n(ref.step(p, f16, 1), prev, cfg)
+        f64 = ref.step(p, f64, s - done)
+        done = s
+        o16.append(f16)
+        hm.append(np.abs(f16 - fmt.W_CLASS[:, None] * prev[None, :]).max(0))
+        ex.append(f64)
+    return o16, hm, ex
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_f16n_steps_within_format_envelope(name):
+    cfg, init, p, f0 = _case(name)
+    cps = [10, 50] if name == "droplet_32" else [10]
+    lat = _lattice(cfg, f0, tile=TILES.get(name))
+    got, done = [], 0
+    for s in cps:
+        lat.step(s - done)
+        done = s
+        got.append(lat.read_populations().cpu().numpy())
+    lat.close()
+    o16, hm, ex = _o16n_and_exact(p, cfg, f0, cps)
+    for s, g, o, h, w in zip(cps, got, o16, hm, ex):
+        r = w.sum(0)
+        bound = 2.0 * _near_max(np.abs(o - w).max(0), cfg) + 2.0 ** -11 * _near_max(h, cfg) + \
+            min(5e-6 * s, 1e-5) * r
+        e = np.abs(g - w).max(0)
+        print(f"  step {s}: max err/bound {float((e / bound).max()):.3f}, "
+              f"format err/rho {float((np.abs(o - w).max(0) / r).max()):.2e}, gpu err/rho {float((e / r).max()):.2e}")
+        assert np.all(e <= bound), s
+        if s == 10:
+            rel = np.abs(g.sum(0) - r) / r
+            liquid = r > 0.5 * (init["rho_L"] + init["rho_V"])
+            print(f"  step 10 density err: liquid {rel[liquid].max():.2e}, vapour {rel[~liquid].max():.2e}")
+            assert rel[liquid].max() < 2e-3 and rel[~liquid].max() < 5e-3
+
+
+def test_f16n_one_step_full_size_sampled():
+    """The 256^3 two-droplet workload in the split step's default launch
+    shape (F16N): one step from the same stored state, at sampled nodes whose
+    collision the oracle computes one by one."""
+    _need_gpu()
+    cfg, init = li.c3_two_droplets()
+    cfg = dict(cfg, storage="f16n", f16_exp=f16_exp_for(1.25 * init["rho_L"]))
+    rho, u = li.init_fields(cfg, init)
+    p = ref.make_params(cfg)
+    f0 = ref.equilibrium(p, rho, u)
+    N = rho.size
+    rng = np.random.default_rng(2026)
+    idx = np.unique(np.concatenate([rng.integers(0, N, 3000),
+                                    np.flatnonzero(np.abs(rho - 0.5 * (init["rho_L"] + init["rho_V"]))
+                                                   < 0.25 * (init["rho_L"] - init["rho_V"]))[::97][:2000]]))
+    lat = _lattice(cfg, f0)
+    print(f"  tile {lat.get_tile()}, samples {idx.size}", flush=True)
+    raw = lat.save_state()[:20 * N * 2].view(torch.int16).reshape(20, N)
+    f_in = fmt.decode_n(_pulled(raw[:19].cpu().numpy().view(np.float16), cfg),
+                        raw[19].cpu().numpy().view(np.float16), cfg)
+    lat.step(1)
+    raw = lat.save_state()[:20 * N * 2].view(torch.int16).reshape(20, N)
+    ti = torch.as_tensor(idx, device=raw.device)
+    h1 = raw[:19, ti].cpu().numpy().view(np.float16)
+    dest = np.stack([((idx // (256 * 256) + ez) % 256 * 256 + (idx // 256 % 256 + ey) % 256) * 256
+                     + (idx % 256 + ex) % 256 for ex, ey, ez in moments.VELOCITIES])
+    rt_dest = raw[19][torch.as_tensor(dest.reshape(-1), device=raw.device)].cpu().numpy().view(np.float16)
+    lat.close()
+    del raw
+    w64 = ref.collide_nodes(p, f_in, idx).T
+    _check_one_step(h1, fmt.encode_n(w64, rt_dest.reshape(19, -1), cfg), w64.sum(0)[None, :], cfg)
+
+
+def _two_droplet_errors(n, steps, storage):
+    cfg, init = li.c3_two_droplets(n=n)
+    ex = dict(f16_exp=f16_exp_for(1.25 * init["rho_L"]), rho_ref=init["rho_V"])
+    rho = {}
+    for st in ("f64", storage):
+        print(f"[gpu] two droplets {n}^3 {st} {steps} steps", flush=True)
+        lat = Lattice(dict(cfg, storage=st, **ex)).init_droplets(init["droplets"], init["rho_L"], init["rho_V"],
+                                                                 init["W"])
+        lat.step(steps)
+        rho[st] = lat.read_fields()["rho"].cpu().numpy()
+        lat.close()
+    w, g = rho["f64"], rho[storage]
+    rel = np.abs(g - w) / w
+    liquid = w > 0.5 * (init["rho_L"] + init["rho_V"])
+    return float(rel[liquid].max()), float(rel[~liquid].max())
+
+
+def test_f16n_keeps_liquid_precision():
+    """The 256^3 two-droplet recipe scaled to 96^3, 400 steps (through the
+    collision): F16N's largest density error against FP64 storage, in the
+    liquid and in the vapour, is below the 2e-3 / 5e-3 caps and at most a
+    third of F16S's."""
+    _need_gpu()
+    n16 = _two_droplet_errors(96, 400, "f16n")
+    s16 = _two_droplet_errors(96, 400, "f16s")
+    print(f"  liquid / vapour: F16N {n16[0]:.2e} / {n16[1]:.2e}, F16S {s16[0]:.2e} / {s16[1]:.2e}")
+    assert n16[0] < 2e-3 and n16[1] < 5e-3
+    assert n16[0] < s16[0] / 3 and n16[1] < s16[1] / 3

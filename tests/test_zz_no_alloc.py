@@ -15,15 +15,18 @@ from paper_1805_08643_amd.binding import Lattice, f16_exp_for
 
 pytestmark = pytest.mark.gpu
 
-ELEM = {"f64": 8, "f32": 4, "f16s": 2}
+ELEM = {"f64": 8, "f32": 4, "f16s": 2, "f16n": 2}
 
 
 def _cases():
     big, big_init = li.c4_sessile(60.0, nx=48, ny=40, nz=20, r0=9.0)
+    mid, mid_init = li.c4_sessile(90.0, nx=40, ny=32, nz=16, r0=8.0)
     small, small_init = li.c4_sessile(120.0, nx=24, ny=20, nz=10, r0=5.0)
     per, per_init = li.c3_two_droplets(n=32)
     return [
         ("walls_48x40x20_60deg_f32", dict(big, storage="f32"), big_init, 3),
+        ("walls_40x32x16_90deg_f16n", dict(mid, storage="f16n", f16_exp=f16_exp_for(1.25 * mid_init["rho_L"])),
+         mid_init, 2),
         ("walls_24x20x10_120deg_f64", dict(small, storage="f64"), small_init, 2),
         ("periodic_32_f16s", dict(per, storage="f16s", rho_ref=per_init["rho_V"],
                                   f16_exp=f16_exp_for(1.25 * per_init["rho_L"])), per_init, 2),
@@ -41,7 +44,7 @@ def test_noalloc_step_bit_identical_to_context_step():
     for name, cfg, init, steps in _cases():
         print(f"[gpu] noalloc {name}: {steps} calls", flush=True)
         N = cfg["nx"] * cfg["ny"] * cfg["nz"]
-        nbytes = 19 * N * ELEM[cfg["storage"]]
+        nbytes = binding.planes(cfg["storage"]) * N * ELEM[cfg["storage"]]
         ref_lat = Lattice(cfg)
         ref_lat.init_droplets(init["droplets"], init["rho_L"], init["rho_V"], init["W"])
         src = _raw(ref_lat, nbytes)
