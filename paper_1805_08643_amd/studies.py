@@ -542,8 +542,8 @@ def cavity_mach(L=80, Re=400.0, speeds=(0.1, 0.3, 0.5), transits=60, storage="f6
 
 def throughput():
     """GPU MLUPS for each standard workload: 32^3 droplet (FP64), 128^3
-    Laplace droplet (FP64, FP32), 256^3 two droplets (FP64, FP32, F16S),
-    384 x 384 x 192 sessile droplet (FP32), and the 256-run batch (FP32,
+    Laplace droplet (FP64, FP32), 256^3 two droplets (FP64, FP32, F16S,
+    F16N), 384 x 384 x 192 sessile droplet (FP32, F16N), and the 256-run batch (FP32,
     F16S), with the kernels and tiles of ``tuning``.  (The oracle's rates on
     the host for the same workloads come from ``bench.py --cpu-workloads``.)"""
     import torch
@@ -553,8 +553,8 @@ def throughput():
     from paper_1805_08643_amd.binding import Batch, f16_exp_for
     work = [("droplet_32", li.c1_droplet, ("f64",), 500),
             ("laplace_128", lambda: li.c2_laplace(24), ("f64", "f32"), 200),
-            ("two_droplets_256", li.c3_two_droplets, ("f64", "f32", "f16s"), 200),
-            ("sessile_384x384x192", lambda: li.c4_sessile(60.0), ("f32",), 200)]
+            ("two_droplets_256", li.c3_two_droplets, ("f64", "f32", "f16s", "f16n"), 200),
+            ("sessile_384x384x192", lambda: li.c4_sessile(60.0), ("f32", "f16n"), 200)]
     out = []
     for name, fn, storages, gsteps in work:
         cfg, init = fn()
