@@ -27,6 +27,7 @@ STEP_TILES = {
     ("sessile_384x384x192", "f32", "fused"): (64, 4, 32),
     ("sessile_384x384x192", "f32", "pairs"): (128, 8, 16),
     ("sessile_384x384x192", "f32", "split"): (128, 4, 48),
+    ("sessile_384x384x192", "f16n", "split"): (128, 8, 32),
 }
 
 # Faster step kernel per (workload, storage); absent: "fused".
