@@ -381,6 +381,15 @@ int32_t lbm_batch_runs(const lbm_batch *b);
  * synchronises; state unchanged. */
 lbm_status lbm_batch_autotune(lbm_batch *b, int32_t trials, int32_t *best_blocks);
 lbm_status lbm_batch_set_blocks(lbm_batch *b, int32_t blocks);
+/* Nodes per work item (a run's tile holds about this many nodes: whole rows
+ * of up to 128 nodes times the z run that reaches it), in [1, 2^24]; rebuilds
+ * the work list and drops captured graphs, and caps the grid at the new tile
+ * count.  With lbm_batch_set_step_mode and lbm_batch_set_blocks it restores a
+ * shape that lbm_batch_autotune chose (the tuning cache of the Python
+ * binding does).  Results are bit for bit the same for every value. */
+lbm_status lbm_batch_set_item_nodes(lbm_batch *b, int32_t item_nodes);
+/* Current step mode, nodes per work item and grid size; any pointer may be NULL. */
+lbm_status lbm_batch_get_tuning(const lbm_batch *b, int32_t *mode, int32_t *item_nodes, int32_t *blocks);
 /* Step kernel of the batch: LBM_STEP_FUSED, LBM_STEP_PAIRS (two nodes per
  * thread; FP32/F16S storage and even nx in every run) or LBM_STEP_SPLIT
  * (pulling and colliding waves; FP32 with even nx or F16S with nx a multiple

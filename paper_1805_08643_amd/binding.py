@@ -117,6 +117,8 @@ SIGNATURES = {
     "lbm_batch_read_populations": (_i32, [_vp, _i32, _vp]),
     "lbm_batch_autotune": (_i32, [_vp, _i32, _P(_i32)]),
     "lbm_batch_set_blocks": (_i32, [_vp, _i32]),
+    "lbm_batch_set_item_nodes": (_i32, [_vp, _i32]),
+    "lbm_batch_get_tuning": (_i32, [_vp, _P(_i32), _P(_i32), _P(_i32)]),
     "lbm_batch_set_step_mode": (_i32, [_vp, _i32]),
     "lbm_batch_get_step_mode": (_i32, [_vp, _P(_i32)]),
     "lbm_batch_kernel_time": (_i32, [_vp, _dp, _P(_i64)]),
@@ -581,6 +583,16 @@ class Batch:
 
     def set_blocks(self, blocks):
         _call("lbm_batch_set_blocks", _vp(self.h), int(blocks))
+
+    def set_item_nodes(self, n):
+        _call("lbm_batch_set_item_nodes", _vp(self.h), int(n))
+        return self
+
+    def tuning(self):
+        """(step mode name, nodes per work item, grid blocks)."""
+        m, it, bl = _i32(0), _i32(0), _i32(0)
+        _call("lbm_batch_get_tuning", _vp(self.h), ctypes.byref(m), ctypes.byref(it), ctypes.byref(bl))
+        return {v: k for k, v in STEP_MODES.items()}[m.value], it.value, bl.value
 
     def set_step_mode(self, mode):
         """mode: "fused", "pairs" or "split"."""

@@ -1537,6 +1537,25 @@ lbm_status lbm_batch_set_blocks(lbm_batch *b, int32_t blocks) {
     return LBM_OK;
 }
 
+lbm_status lbm_batch_set_item_nodes(lbm_batch *b, int32_t item_nodes) {
+    if (!b) return fail(LBM_ERR_INVALID_ARG, "batch is NULL");
+    if (item_nodes < 1 || item_nodes > (1 << 24))
+        return fail(LBM_ERR_INVALID_ARG, "item_nodes %d outside [1, 2^24]", item_nodes);
+    b->item_nodes = item_nodes;
+    lbm_status s = batch_build(b);
+    if (s) return s;
+    b->blocks = std::min(b->blocks, b->total_tiles);
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_get_tuning(const lbm_batch *b, int32_t *mode, int32_t *item_nodes, int32_t *blocks) {
+    if (!b) return fail(LBM_ERR_INVALID_ARG, "batch is NULL");
+    if (mode) *mode = b->mode;
+    if (item_nodes) *item_nodes = b->item_nodes;
+    if (blocks) *blocks = b->blocks;
+    return LBM_OK;
+}
+
 lbm_status lbm_batch_set_step_mode(lbm_batch *b, int32_t mode) {
     if (!b) return fail(LBM_ERR_INVALID_ARG, "batch is NULL");
     if (mode != LBM_STEP_FUSED && mode != LBM_STEP_PAIRS && mode != LBM_STEP_SPLIT)

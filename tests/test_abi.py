@@ -126,6 +126,13 @@ def test_batch_validation():
     assert n.value >= 2 * binding.lbm_workspace_bytes(a)
 
 
+def test_batch_tuning_calls_reject_null():
+    L = binding.lib()
+    m = ctypes.c_int32(0)
+    assert L.lbm_batch_set_item_nodes(None, 4096) == -1
+    assert L.lbm_batch_get_tuning(None, ctypes.byref(m), None, None) == -1
+
+
 def test_status_strings():
     assert binding.lbm_status_string(0) == "ok"
     assert binding.lbm_status_string(-4) == "non-finite populations"
