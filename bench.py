@@ -190,6 +190,37 @@ def time_steps(lat, steps, warmup, kernel_timing):
     return ms, wall, kms
 
 
+def precision_check(steps=100):
+    """Errors of FP32, F16S and F16N storage against FP64 storage on the
+    benchmark workload after `steps` steps from the same initial droplets:
+    largest relative density error in the liquid and in the vapour over the
+    whole lattice, and the relative mass drift; with the bounds the tests
+    hold them to (density: 1e-5 for FP32, 2e-3 liquid / 5e-3 vapour for the
+    16-bit formats)."""
+    import torch
+    out, ref = {"steps": steps, "reference": "FP64 storage on the GPU (matches the FP64 oracle to 1e-12)",
+                "bounds": {"f32": 1e-5, "f16": {"liquid": 2e-3, "vapour": 5e-3}}}, None
+    for st in ("f64", "f32", "f16s", "f16n"):
+        lat, cfg, init = make_lattice(st, "nonorth")
+        m0 = lat.diagnostics()["mass"]
+        lat.step(steps)
+        rho = lat.read_fields()["rho"]
+        m1 = lat.diagnostics()["mass"]
+        lat.close()
+        del lat
+        if ref is None:
+            ref = rho
+            liquid = ref > 0.5 * (init["rho_L"] + init["rho_V"])
+        else:
+            rel = (rho - ref).abs() / ref
+            out[st] = {"rho_max_rel_err_liquid": float(rel[liquid].max()),
+                       "rho_max_rel_err_vapour": float(rel[~liquid].max()),
+                       "mass_drift": (m1 - m0) / m0}
+            del rho, rel
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_batch(storage, steps=40, graph_steps=10):
     """Batched workload: 256 independent periodic droplet runs, L ~ U{32, 48,
     64, 96}, T/Tc ~ U[0.6, 0.9], tau_nu ~ U[0.6, 1.2] (seed 1805), one
@@ -455,6 +486,7 @@ def main():
             torch.cuda.empty_cache()
         out["variants_mlups"] = var
         out["batch"] = {st: bench_batch(st) for st in ("f32", "f16s")}
+        out["precision"] = precision_check()
     cp = ceiling_probe(reps=10, quick=True)["rows"]
     out["roofline"]["copy_probe_GBps"] = cp[0]["GBps_read_plus_write"]
     out["roofline"]["stream19_probe_GBps"] = cp[1]["GBps_read_plus_write"]

@@ -33,8 +33,13 @@ returns plain dicts (one line of JSON per run is printed as it finishes).
   contact_cs Sessile droplet with the C-S EOS at T = 0.7 T_c on
              384 x 384 x 192, gravity 1e-6 along -z, 60 / 90 / 120 deg, FP32.
   throughput GPU MLUPS for each standard workload.
-  precision  FP32 and shifted-FP16 storage against FP64 storage on the 256^3
-             two-droplet run (steps 100, 500, 1000, 2000).
+  precision  FP32 and 16-bit storage (F16S with three shifts, F16N) against
+             FP64 storage on the 256^3 two-droplet run (steps 100, 500, 1000,
+             2000).
+  precision_results  per-result errors of FP32, F16S and F16N storage against
+             FP64 storage on the 128^3 Laplace droplets at rest: coexistence
+             densities, Delta p, surface tension, spurious currents, density
+             field.
 
 ``python -m paper_1805_08643_amd.studies <name> [<name> ...] [--out-dir DIR]``
 """
@@ -629,6 +634,52 @@ def laplace_cs(ops=("nonorth", "orth"), storages=("f64", "f32"), radii=(24, 28, 
     return out
 
 
+def precision_results(storages=("f64", "f32", "f16s", "f16n"), radii=(24, 32, 40), steps=20000):
+    """Error of each storage format against FP64 storage per result, on the
+    128^3 Laplace droplets (C-S EOS at T = 0.7 T_c, density ratio 38.5) run to
+    rest: the coexistence densities rho_L and rho_V, the pressure jump Delta p
+    of each radius and the surface tension from the Laplace fit, the
+    spurious-current magnitude max |u|, and the density field (largest
+    relative difference over the lattice).  F16S shifts by rho_V; F16N by the
+    binary16 density of the node that pulls each population."""
+    import torch
+
+    import lbm_inputs as li
+    from paper_1805_08643_amd.binding import f16_exp_for
+    out, runs, fields = [], {}, {}
+    for st in storages:
+        for r0 in radii:
+            cfg, init = li.c2_laplace(r0)
+            c = init["droplets"][0]["center"]
+            lat = _lattice(dict(cfg, storage=st, rho_ref=init["rho_V"], f16_exp=f16_exp_for(1.25 * init["rho_L"])))
+            lat.init_droplets(init["droplets"], init["rho_L"], init["rho_V"], init["W"])
+            lat.step(steps)
+            runs[(st, r0)] = _droplet(lat, c, float(r0), init["W"])
+            fields[(st, r0)] = lat.read_fields()["rho"].cpu()
+            lat.close()
+        x = np.array([1.0 / runs[(st, r)]["R_d"] for r in radii])
+        y = np.array([runs[(st, r)]["dp"] for r in radii])
+        runs[(st, "fit")] = dict(zip(("slope", "intercept", "r2"), _linfit(x, y)))
+    rel = lambda a, b: abs(a - b) / abs(b)
+    for st in storages:
+        row = dict(study="precision_results", storage=st, steps=steps, radii=list(radii),
+                   surface_tension=runs[(st, "fit")]["slope"] / 2, laplace_r2=runs[(st, "fit")]["r2"], per_radius=[])
+        for r0 in radii:
+            a, b = runs[(st, r0)], runs[("f64", r0)]
+            d = dict(r0=r0, **{k: a[k] for k in ("rho_L", "rho_V", "dp", "R_d", "max_u")})
+            if st != "f64":
+                f, g = fields[(st, r0)], fields[("f64", r0)]
+                d.update(rho_L_rel_err=rel(a["rho_L"], b["rho_L"]), rho_V_rel_err=rel(a["rho_V"], b["rho_V"]),
+                         dp_rel_err=rel(a["dp"], b["dp"]), max_u_rel_err=rel(a["max_u"], b["max_u"]),
+                         rho_field_max_rel_err=float(((f - g).abs() / g).max()))
+            row["per_radius"].append(d)
+        if st != "f64":
+            row["surface_tension_rel_err"] = rel(row["surface_tension"], runs[("f64", "fit")]["slope"] / 2)
+        out.append(_emit(row))
+    torch.cuda.empty_cache()
+    return out
+
+
 def precision(steps=(100, 500, 1000, 2000), n=256, crop=64):
     """Density error of FP32 and 16-bit storage against FP64 storage on the
     central crop^3 box, the droplet-pair observables, and the relative mass
@@ -688,7 +739,8 @@ def precision(steps=(100, 500, 1000, 2000), n=256, crop=64):
 
 STUDIES = {f.__name__: f for f in (table1, stability, laplace, spurious, contact, flat, table2, orth_readings,
                                    viscosity_ratio,
-                                   cavity_cost, cavity_mach, laplace_cs, contact_cs, precision, throughput)}
+                                   cavity_cost, cavity_mach, laplace_cs, contact_cs, precision, precision_results,
+                                   throughput)}
 
 
 def main(argv=None):
