@@ -485,7 +485,7 @@ def main():
             del l2
             torch.cuda.empty_cache()
         out["variants_mlups"] = var
-        out["batch"] = {st: bench_batch(st) for st in ("f32", "f16s")}
+        out["batch"] = {st: bench_batch(st) for st in ("f32", "f16s", "f16n")}
         out["precision"] = precision_check()
     cp = ceiling_probe(reps=10, quick=True)["rows"]
     out["roofline"]["copy_probe_GBps"] = cp[0]["GBps_read_plus_write"]

@@ -71,7 +71,7 @@ enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16S = 2, LBM_STORE_F16N 
  * from their shifts only by what streaming and collision changed in one step,
  * instead of by the whole liquid-vapour density contrast of F16S.  rho_ref is
  * ignored.  F16N runs the split step only (nx a multiple of 4, walls only on
- * z, no batches); its step moves 40 instead of 38 values of 2 bytes per node. */
+ * z; batches too); its step moves 40 instead of 38 values of 2 bytes per node. */
 
 /* Pseudopotential form (text after Eq. (15)). */
 enum { LBM_PSI_SQRT_CS = 0, /* psi = sqrt(2 (p_EOS - rho/3) / G), C-S p_EOS, Eq. (58) */
@@ -393,7 +393,8 @@ lbm_status lbm_batch_get_tuning(const lbm_batch *b, int32_t *mode, int32_t *item
 /* Step kernel of the batch: LBM_STEP_FUSED, LBM_STEP_PAIRS (two nodes per
  * thread; FP32/F16S storage and even nx in every run) or LBM_STEP_SPLIT
  * (pulling and colliding waves; FP32 with even nx or F16S with nx a multiple
- * of 4 in every run); otherwise LBM_ERR_UNSUPPORTED.  A new batch uses
+ * of 4 in every run; the only mode of F16N batches); otherwise
+ * LBM_ERR_UNSUPPORTED.  A new batch uses
  * LBM_STEP_SPLIT where it applies to every run, else LBM_STEP_PAIRS where that
  * applies, else LBM_STEP_FUSED.  Rebuilds the work list and drops captured
  * graphs; results are bit for bit the same in all modes. */

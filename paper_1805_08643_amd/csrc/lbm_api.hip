@@ -1219,8 +1219,6 @@ lbm_status batch_validate(const lbm_params *runs, int32_t n) {
         if (s) return fail(s, "run %d: %s", k, g_err.c_str());
         if (runs[k].wall_z || runs[k].wall_x || runs[k].wall_y)
             return fail(LBM_ERR_UNSUPPORTED, "run %d: batched runs must be periodic", k);
-        if (runs[k].storage == LBM_STORE_F16N)
-            return fail(LBM_ERR_UNSUPPORTED, "run %d: batched runs take F64, F32 or F16S storage", k);
         if (runs[k].op != runs[0].op || runs[k].storage != runs[0].storage)
             return fail(LBM_ERR_INVALID_ARG, "run %d: all runs must share op and storage", k);
     }
@@ -1256,7 +1254,8 @@ lbm_status batch_build(lbm_batch *b) {
         d.offB = b->run_off[k] + c->L.B;
         d.tile_begin = tiles;
         tiles += c->g.ntiles;
-        if (b->mode == LBM_STEP_SPLIT && split_ring2(c->g.tx, c->g.ty)) b->ring2 = true;
+        // F16N's pullers take the whole halo ring (see launch_step).
+        if (b->mode == LBM_STEP_SPLIT && b->storage != ST_F16N && split_ring2(c->g.tx, c->g.ty)) b->ring2 = true;
         threads = b->mode == LBM_STEP_SPLIT ? 2 * SPLIT_ROLE
                                             : std::max(threads, block_threads(c->g.tx, c->g.ty, npt_of(b->mode, b->storage)));
         smem = b->mode == LBM_STEP_SPLIT ? 0 : std::max(smem, step_smem(c, c->g));
@@ -1291,6 +1290,10 @@ lbm_status batch_launch(lbm_batch *b, hipStream_t st, int parity, int blocks) {
     LBM_SCASE4(ST_F32, OP_ORTH)
     LBM_SCASE4(ST_F16S, OP_NONORTH)
     LBM_SCASE4(ST_F16S, OP_ORTH)
+    LBM_SCASE(ST_F16N, OP_NONORTH, false, false)
+    LBM_SCASE(ST_F16N, OP_NONORTH, false, true)
+    LBM_SCASE(ST_F16N, OP_ORTH, false, false)
+    LBM_SCASE(ST_F16N, OP_ORTH, false, true)
 #undef LBM_SCASE4
 #undef LBM_SCASE
 #define LBM_BCASE(s, o, pr)                                                                                   \
@@ -1566,8 +1569,11 @@ lbm_status lbm_batch_set_step_mode(lbm_batch *b, int32_t mode) {
             if (!pairs_apply(b->runs[k]->p))
                 return fail(LBM_ERR_UNSUPPORTED, "run %zu: pair mode needs FP32/F16S storage and even nx", k);
     }
+    if (b->storage == ST_F16N && mode != LBM_STEP_SPLIT)
+        return fail(LBM_ERR_UNSUPPORTED, "F16N storage runs the split step only");
     if (mode == LBM_STEP_SPLIT && !batch_split_apply(b))
-        return fail(LBM_ERR_UNSUPPORTED, "split mode needs FP32 with even nx or F16S with nx a multiple of 4 in every run");
+        return fail(LBM_ERR_UNSUPPORTED, "split mode needs FP32 with even nx or F16S or F16N with nx a multiple of 4 in "
+                    "every run");
     b->mode = mode;
     lbm_status s = batch_build(b);
     if (s) return s;
@@ -1601,7 +1607,8 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t trials, int32_t *best_blocks
     float best = 1e30f;
     int best_items = b->item_nodes, best_blk = b->blocks;
     int best_mode = b->mode;
-    std::vector<int> modes{LBM_STEP_FUSED};
+    std::vector<int> modes;
+    if (b->storage != ST_F16N) modes.push_back(LBM_STEP_FUSED);  // F16N runs the split step only
     bool all_pairs = true;
     for (lbm_ctx *c : b->runs) all_pairs = all_pairs && pairs_apply(c->p);
     if (all_pairs) modes.push_back(LBM_STEP_PAIRS);

@@ -548,8 +548,8 @@ def cavity_mach(L=80, Re=400.0, speeds=(0.1, 0.3, 0.5), transits=60, storage="f6
 def throughput():
     """GPU MLUPS for each standard workload: 32^3 droplet (FP64), 128^3
     Laplace droplet (FP64, FP32), 256^3 two droplets (FP64, FP32, F16S,
-    F16N), 384 x 384 x 192 sessile droplet (FP32, F16N), and the 256-run batch (FP32,
-    F16S), with the kernels and tiles of ``tuning``.  (The oracle's rates on
+    F16N), 384 x 384 x 192 sessile droplet (FP32, F16N), and the 256-run batch (FP32, F16S,
+    F16N), with the kernels and tiles of ``tuning``.  (The oracle's rates on
     the host for the same workloads come from ``bench.py --cpu-workloads``.)"""
     import torch
 
@@ -585,7 +585,7 @@ def throughput():
         out.append(_emit(row))
     runs = li.c5_batch()
     row = dict(study="throughput", workload="batch_256_runs")
-    for st in ("f32", "f16s"):
+    for st in ("f32", "f16s", "f16n"):
         cfgs = [dict(pp, storage=st, rho_ref=init["rho_V"], f16_exp=f16_exp_for(1.25 * init["rho_L"]))
                 for pp, init in runs]
         b = Batch(cfgs)

@@ -148,7 +148,7 @@ def test_make_params_mapping():
 def test_f16n_layout_and_limits():
     """F16N holds a twentieth plane (the reference densities) beside the 19
     populations of 2 bytes, and runs the split step only: nx a multiple of 4,
-    walls only on z, no batches."""
+    walls only on z (batches of such runs too)."""
     p = binding.lbm_params_default()
     p.storage = binding.STORAGE["f16s"]
     n16s = binding.lbm_workspace_bytes(p)
@@ -167,7 +167,8 @@ def test_f16n_layout_and_limits():
     assert L.lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == -5
     p.wall_x = 0
     arr = (binding.LbmParams * 2)(p, p)
-    assert L.lbm_batch_workspace_bytes(arr, 2, ctypes.byref(n)) == -5
+    assert L.lbm_batch_workspace_bytes(arr, 2, ctypes.byref(n)) == 0
+    assert n.value >= 2 * n16n
     assert binding.algorithmic_bytes_per_node("f16n") == 80
 
 

@@ -55,7 +55,7 @@ def test_batch_fp64_matches_oracle(graph_steps):
     b.close()
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16s"])
+@pytest.mark.parametrize("storage", ["f32", "f16s", "f16n"])
 def test_batch_bit_identical_to_single_lattices(storage):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -95,7 +95,7 @@ def test_batch_step_modes_bit_identical(storage):
         assert np.array_equal(out["pairs"][k], out["split"][k]), k
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16s"])
+@pytest.mark.parametrize("storage", ["f32", "f16s", "f16n"])
 def test_batch_split_wide_run(storage):
     """A run 132 nodes wide takes 128-wide split tiles, whose halo ring is
     larger than the pulling waves: the batch launches the variant in which
@@ -115,7 +115,8 @@ def test_batch_split_wide_run(storage):
     b.step(4, 3)
     for k, (q, i) in enumerate(runs):
         lat = Lattice(q)
-        lat.set_step_mode("fused")
+        if storage != "f16n":  # F16N has the split step only
+            lat.set_step_mode("fused")
         lat.init_fields(*li.init_fields(q, i)).step(4)
         got = b.pops(k)
         assert np.isfinite(got).all(), k
@@ -124,7 +125,7 @@ def test_batch_split_wide_run(storage):
     b.close()
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16s"])
+@pytest.mark.parametrize("storage", ["f32", "f16s", "f16n"])
 def test_batch_split_store_policies_bit_identical(storage):
     """Non-temporal and cached population stores give the same bits in a
     batch, in plain launches and graph replays."""
@@ -145,7 +146,8 @@ def test_batch_split_store_policies_bit_identical(storage):
 
 
 def test_batch_split_rejects_unsuitable_runs():
-    """F16S split needs nx % 4 == 0 in every run."""
+    """F16S split needs nx % 4 == 0 in every run; an F16N batch runs the
+    split step only."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     runs = _runs("f16s", sizes=(32, 18))
@@ -155,6 +157,12 @@ def test_batch_split_rejects_unsuitable_runs():
     assert e.value.status == -5
     assert b.step_mode() == "pairs"
     b.close()
+    fn = Batch([r[0] for r in _runs("f16n", sizes=(32, 20))])
+    assert fn.step_mode() == "split"
+    with pytest.raises(binding.LbmError) as e:
+        fn.set_step_mode("fused")
+    assert e.value.status == -5 and fn.step_mode() == "split"
+    fn.close()
 
 
 def test_batch_full_workload_sampled_runs():
