@@ -26,8 +26,6 @@ returns plain dicts (one line of JSON per run is printed as it finishes).
              and nu_V / nu_L in {1, 2, 5, 10}; maximum spurious velocity.
   cavity_cost  Appendix B, Table III: time of 5000 iterations of the
              single-phase lid-driven cavity, L = 60, 80, 110, both operators.
-  cavity_mach  Appendix B, Figs. 9-10: cavity at L = 80, Re = 400, lid speed
-             0.1, 0.3, 0.5; centre-line profiles, operators compared.
   laplace_cs Laplace law with the C-S EOS at T = 0.7 T_c, a = 0.5, 128^3,
              r0 in 12..28, FP64 and FP32 storage, both operators.
   contact_cs Sessile droplet with the C-S EOS at T = 0.7 T_c on
@@ -506,45 +504,6 @@ def cavity_cost(sizes=(60, 80, 110), steps=5000, storages=("f64", "f32")):
     return out
 
 
-def cavity_mach(L=80, Re=400.0, speeds=(0.1, 0.3, 0.5), transits=60, storage="f64"):
-    """Appendix B, Figs. 9-10: steady cavity flow at Re = 400 for lid speeds
-    U (Ma = U / c_s); profiles u_y(x) / U on the line y = z = L/2 and
-    u_x(y) / U on x = z = L/2 (means of the two central nodes when L is
-    even), both operators, run for `transits` lid transit times L / U."""
-    out = []
-    h = L // 2
-    for U in speeds:
-        for op in ("nonorth", "orth"):
-            lat = _lattice(_cavity_cfg(L, U, Re, op, storage))
-            lat.init_fields(np.ones(L ** 3), np.zeros((3, L ** 3)))
-            steps = int(transits * L / U)
-            lat.step(steps)
-            u = lat.read_fields()["u"].cpu().numpy().reshape(3, L, L, L)  # (comp, z, y, x)
-            d = lat.diagnostics()
-            lat.close()
-            zc = slice(h - 1, h + 1) if L % 2 == 0 else slice(h, h + 1)
-            uy_x = u[1][zc][:, zc].mean(axis=(0, 1)) / U      # along x at y = z = L/2
-            ux_y = u[0][zc][:, :, zc].mean(axis=(0, 2)) / U   # along y at x = z = L/2
-            out.append(_emit(dict(study="cavity_mach", L=L, Re=Re, U=U, Ma=U * math.sqrt(3.0), op=op, steps=steps,
-                                  uy_x=[round(float(v), 6) for v in uy_x], ux_y=[round(float(v), 6) for v in ux_y],
-                                  max_u=d["max_u"], mass=d["mass"], nonfinite=d["nonfinite"])))
-    # operator and Mach comparisons
-    by = {(r["U"], r["op"]): r for r in out}
-    summary = []
-    for U in speeds:
-        a, b = by[(U, "nonorth")], by[(U, "orth")]
-        summary.append(dict(U=U, max_diff_ops_uy=float(np.abs(np.array(a["uy_x"]) - np.array(b["uy_x"])).max()),
-                            max_diff_ops_ux=float(np.abs(np.array(a["ux_y"]) - np.array(b["ux_y"])).max())))
-    for U in speeds[1:]:
-        for op in ("nonorth", "orth"):
-            a, b = by[(U, op)], by[(speeds[0], op)]
-            summary.append(dict(U=U, op=op, vs_U=speeds[0],
-                                max_diff_uy=float(np.abs(np.array(a["uy_x"]) - np.array(b["uy_x"])).max()),
-                                max_diff_ux=float(np.abs(np.array(a["ux_y"]) - np.array(b["ux_y"])).max())))
-    out.append(_emit(dict(study="cavity_mach_summary", rows=summary)))
-    return out
-
-
 def throughput():
     """GPU MLUPS for each standard workload: 32^3 droplet (FP64), 128^3
     Laplace droplet (FP64, FP32), 256^3 two droplets (FP64, FP32, F16S,
@@ -739,7 +698,7 @@ def precision(steps=(100, 500, 1000, 2000), n=256, crop=64):
 
 STUDIES = {f.__name__: f for f in (table1, stability, laplace, spurious, contact, flat, table2, orth_readings,
                                    viscosity_ratio,
-                                   cavity_cost, cavity_mach, laplace_cs, contact_cs, precision, precision_results,
+                                   cavity_cost, laplace_cs, contact_cs, precision, precision_results,
                                    throughput)}
 
 
