@@ -78,6 +78,7 @@ template <class R> struct Phys {
     R nuV, dnu, vrhoV, vinv;
     R lid6[3];
     R w_eps, w_epsj, w_epsj2, w_xx;
+    R whs[3];  // class weights times 2^h_exp (exact): F16N's stored shift rt w_a 2^e is rt * whs in one rounding
     __device__ inline void load(const PhysD &d) {
         G = (R)d.G;
         a = (R)d.a;
@@ -112,6 +113,9 @@ template <class R> struct Phys {
         shs[0] = shift[0] * hs;
         shs[1] = shift[1] * hs;
         shs[2] = shift[2] * hs;
+        whs[0] = (R)(1.0 / 3.0) * hs;
+        whs[1] = (R)(1.0 / 18.0) * hs;
+        whs[2] = (R)(1.0 / 36.0) * hs;
         psi_form = d.psi_form;
         visc = d.visc;
         nuV = (R)d.nuV;
@@ -133,6 +137,7 @@ template <class R> struct Phys {
     }
     __device__ inline R sh(int a_) const { return a_ == 0 ? shift[0] : (a_ <= 6 ? shift[1] : shift[2]); }
     __device__ inline R shh(int a_) const { return a_ == 0 ? shs[0] : (a_ <= 6 ? shs[1] : shs[2]); }
+    __device__ inline R wh(int a_) const { return a_ == 0 ? whs[0] : (a_ <= 6 ? whs[1] : whs[2]); }
 };
 
 // ---------------------------------------------------------------------------
