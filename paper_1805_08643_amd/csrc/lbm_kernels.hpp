@@ -1382,8 +1382,10 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
                     const bool back = (ez(a) < 0 && bot) || (ez(a) > 0 && top);
                     const uint16_t *pl = back ? nmid : (ez(a) < 0 ? nlo : (ez(a) > 0 ? nhi : nmid));
                     const int pos = back ? cin + k : cin + k + ex(a) + ey(a) * SX;
-                    // rt w_a 2^e: the same bits as (rt w_a) 2^e, since 2^e is exact.
-                    out.put_sh(k, a, f[a], nref_val(pl[pos]) * P.wh(a), P.hs);
+                    // rt w_a 2^e: the same bits as (rt w_a) 2^e, since 2^e is exact.  Written
+                    // as a fused multiply-add with a zero addend (the same single rounding
+                    // of a positive product) so that the binary16 rt enters it directly.
+                    out.put_sh(k, a, f[a], __builtin_fmaf(nref_val(pl[pos]), P.wh(a), 0.0f), P.hs);
                 }
             } else {
 #pragma unroll
