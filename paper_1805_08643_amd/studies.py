@@ -30,6 +30,11 @@ returns plain dicts (one line of JSON per run is printed as it finishes).
              r0 in 12..28, FP64 and FP32 storage, both operators.
   contact_cs Sessile droplet with the C-S EOS at T = 0.7 T_c on
              384 x 384 x 192, gravity 1e-6 along -z, 60 / 90 / 120 deg, FP32.
+  contact_precision  the same wall-bounded configuration with gravity in
+             FP64, FP32 and F16N storage: contact angle, density field and
+             spurious currents against FP64 storage.
+  storage_drift  mass drift of each storage format over 50,000 steps of a
+             96 x 96 x 48 sessile droplet, with and without gravity.
   throughput GPU MLUPS for each standard workload.
   precision  FP32 and 16-bit storage (F16S with three shifts, F16N) against
              FP64 storage on the 256^3 two-droplet run (steps 100, 500, 1000,
@@ -282,6 +287,75 @@ def contact_cs(thetas=(60.0, 90.0, 120.0), steps=50000, storage="f32", gravity=(
         ang, fit, d = _sessile(cfg, init["droplets"][0], init["rho_L"], init["rho_V"], init["W"], steps, storage)
         out.append(_emit(dict(study="contact_cs", theta_prescribed=th, theta_measured=ang, fit=fit, steps=steps,
                               storage=storage, gravity=list(cfg["gravity"]), max_u=d["max_u"], mass=d["mass"], seconds=round(time.time() - t0, 1))))
+    return out
+
+
+def contact_precision(thetas=(60.0, 90.0, 120.0), steps=50000, storages=("f64", "f32", "f16n")):
+    """The wall-bounded configuration (384 x 384 x 192 sessile droplet, C-S
+    EOS at T = 0.7 T_c, gravity 1e-6 along -z, Eq. (57) wetting layer) in
+    each storage format for `steps` steps: the measured contact angle, the
+    density field and the spurious currents of FP32 and F16N against the same
+    run in FP64 storage."""
+    import torch
+
+    import lbm_inputs as li
+    from paper_1805_08643_amd.binding import f16_exp_for
+    out = []
+    for th in thetas:
+        cfg, init = li.c4_sessile(th)
+        rl, rv = init["rho_L"], init["rho_V"]
+        ref = None
+        for st in storages:
+            t0 = time.time()
+            c = dict(cfg, storage=st, rho_ref=rv, f16_exp=f16_exp_for(1.25 * rl))
+            lat = _lattice(c)
+            lat.init_droplets(init["droplets"], rl, rv, init["W"])
+            m0 = lat.diagnostics()["mass"]
+            lat.step(steps)
+            rho = lat.read_fields()["rho"].cpu().numpy()
+            d = lat.diagnostics()
+            lat.close()
+            torch.cuda.empty_cache()
+            ang, fit = contact_angle(rho, cfg["nx"], cfg["ny"], cfg["nz"], 0.5 * (rl + rv))
+            row = dict(study="contact_precision", theta_prescribed=th, storage=st, steps=steps, theta_measured=ang,
+                       max_u=d["max_u"], mass_drift=(d["mass"] - m0) / m0, seconds=round(time.time() - t0, 1))
+            if ref is None:
+                ref = (rho, ang, d["max_u"])
+            else:
+                rel = np.abs(rho - ref[0]) / ref[0]
+                liquid = ref[0] > 0.5 * (rl + rv)
+                row.update(theta_err_deg=ang - ref[1], max_u_rel_err=abs(d["max_u"] - ref[2]) / ref[2],
+                           rho_max_rel_err_liquid=float(rel[liquid].max()),
+                           rho_max_rel_err_vapour=float(rel[~liquid].max()))
+            out.append(_emit(row))
+        del ref
+    return out
+
+
+def storage_drift(n=96, nz=48, r0=12.0, theta=60.0, steps=50000, every=5000,
+                  storages=("f64", "f32", "f16s", "f16n"), gravity=(True, False)):
+    """Relative mass drift over a long run of a small sessile droplet (the
+    wall-bounded configuration scaled to n x n x nz) in each storage format,
+    every `every` steps, with and without gravity."""
+    import lbm_inputs as li
+    from paper_1805_08643_amd.binding import f16_exp_for
+    out = []
+    for gr in gravity:
+        cfg, init = li.c4_sessile(theta, nx=n, ny=n, nz=nz, r0=r0)
+        if not gr:
+            cfg = dict(cfg, gravity=(0.0, 0.0, 0.0))
+        for st in storages:
+            c = dict(cfg, storage=st, rho_ref=init["rho_V"], f16_exp=f16_exp_for(1.25 * init["rho_L"]))
+            lat = _lattice(c)
+            lat.init_droplets(init["droplets"], init["rho_L"], init["rho_V"], init["W"])
+            m0 = lat.diagnostics()["mass"]
+            drift = []
+            for _ in range(steps // every):
+                lat.step(every)
+                drift.append((lat.diagnostics()["mass"] - m0) / m0)
+            lat.close()
+            out.append(_emit(dict(study="storage_drift", storage=st, gravity=list(cfg["gravity"]), size=[n, n, nz],
+                                  theta=theta, every=every, mass_drift=drift)))
     return out
 
 
@@ -698,7 +772,8 @@ def precision(steps=(100, 500, 1000, 2000), n=256, crop=64):
 
 STUDIES = {f.__name__: f for f in (table1, stability, laplace, spurious, contact, flat, table2, orth_readings,
                                    viscosity_ratio,
-                                   cavity_cost, laplace_cs, contact_cs, precision, precision_results,
+                                   cavity_cost, laplace_cs, contact_cs, contact_precision, precision,
+                                   precision_results, storage_drift,
                                    throughput)}
 
 
