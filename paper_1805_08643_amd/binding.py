@@ -641,6 +641,12 @@ def planes(storage: str) -> int:
     return 20 if storage == "f16n" else 19
 
 
+def population_bytes(storage: str, n: int) -> int:
+    """Bytes of one population buffer of n nodes (the raw state without the
+    step counter): the planes, then F16N's 16-byte rounding seed."""
+    return planes(storage) * n * storage_bytes(storage) + (16 if storage == "f16n" else 0)
+
+
 def algorithmic_bytes_per_node(storage: str) -> int:
     """19 population reads + 19 writes per lattice update (F16N: 20 + 20,
     with the reference densities)."""

@@ -53,7 +53,11 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 size_t elem_bytes(int storage) { return storage == LBM_STORE_F64 ? 8 : (storage == LBM_STORE_F32 ? 4 : 2); }
 // Storage elements per node of a population array (19 directions, plus the
 // reference plane of F16N).
-size_t pop_elems(int storage) { return (size_t)planes_of(storage); }
+// Bytes of one population buffer: the planes of N nodes, then the tail
+// (F16N: the rounding seed).
+size_t pop_bytes(int storage, size_t N) {
+    return ((size_t)planes_of(storage) * N + (size_t)tail_elems(storage)) * elem_bytes(storage);
+}
 size_t real_bytes(int storage) { return storage == LBM_STORE_F64 ? 8 : 4; }
 
 bool rate_ok(double s) { return std::isfinite(s) && s > 0.0 && s < 2.0; }
@@ -175,7 +179,7 @@ struct Layout {
 Layout layout_of(const lbm_params &p) {
     const size_t N = (size_t)p.nx * p.ny * p.nz;
     const size_t plane = (size_t)p.nx * p.ny;
-    const size_t pops = align_up(pop_elems(p.storage) * N * elem_bytes(p.storage));
+    const size_t pops = align_up(pop_bytes(p.storage, N));
     Layout L{};
     size_t off = 0;
     L.A = off;
@@ -569,7 +573,7 @@ lbm_status one_step(lbm_ctx *c) {
     lbm_status s = launch_walls(c, c->state());
     if (s) return s;
     if (c->write_check) {
-        const long long words = (long long)pop_elems(c->p.storage) * c->g.N * (long long)elem_bytes(c->p.storage) / 2;
+        const long long words = (long long)(pop_bytes(c->p.storage, (size_t)c->g.N) / 2);
         hipLaunchKernelGGL(k_fill_ones, dim3(grid1d(words, 256)), dim3(256), 0, c->stream,
                            (uint16_t *)c->other(), words);
         HIP_TRY(hipGetLastError());
@@ -942,7 +946,7 @@ lbm_status lbm_diagnostics(lbm_ctx *c, const lbm_diag_request *req, lbm_diag *ou
 
 lbm_status lbm_state_bytes(const lbm_ctx *c, size_t *bytes) {
     if (!c || !bytes) return fail(LBM_ERR_INVALID_ARG, "null argument");
-    *bytes = pop_elems(c->p.storage) * (size_t)c->g.N * elem_bytes(c->p.storage) + sizeof(int64_t);
+    *bytes = pop_bytes(c->p.storage, (size_t)c->g.N) + sizeof(int64_t);
     return LBM_OK;
 }
 

@@ -40,6 +40,9 @@ enum { ST_F64 = 0, ST_F32 = 1, ST_F16S = 2, ST_F16N = 3 };
 // Direction planes of a population array: F16N adds a twentieth plane of
 // reference densities.
 __host__ __device__ constexpr int planes_of(int s) { return s == ST_F16N ? 20 : 19; }
+// Storage elements after the planes of a population buffer: F16N keeps the
+// seed of its stochastic rounding there (one 32-bit word, padded to 16 bytes).
+__host__ __device__ constexpr int tail_elems(int s) { return s == ST_F16N ? 8 : 0; }
 enum { PSI_SQRT_CS = 0, PSI_EXP = 1 };
 
 // ---------------------------------------------------------------------------
@@ -239,6 +242,49 @@ struct NodeShift {
     __device__ inline float operator()(int a) const { return a == 0 ? s[0] : (a <= 6 ? s[1] : s[2]); }
 };
 
+// Stochastic rounding of the F16N step's stores.  Every step reads a seed
+// from the source buffer's tail word and writes seed + 1 to the destination's,
+// so the dither is a function of the state (deterministic, the same on graph
+// replay and across the single-lattice, batched and allocation-free steps)
+// and changes from step to step.  A value that the step moves by less than
+// half a binary16 unit then keeps its change in expectation instead of being
+// rounded back every step (stagnation), which is what makes nearest rounding
+// drift in mass and density over long quasi-static runs.
+//
+// mix32: a 32-bit integer finaliser (xorshift-multiply rounds with the
+// constants of C. Wellons' "lowbias32"); key mixes the seed once per step,
+// node_hash the node index with it.
+__host__ __device__ constexpr uint32_t mix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x7FEB352Du;
+    h ^= h >> 15;
+    h *= 0x846CA68Bu;
+    h ^= h >> 16;
+    return h;
+}
+__host__ __device__ constexpr uint32_t sr_key(uint32_t seed) { return mix32(seed + 0x9E3779B9u); }
+__host__ __device__ constexpr uint32_t sr_node(uint32_t key, uint32_t node) { return mix32(node ^ key); }
+// 13-bit dither of direction a at a node whose hash is nh: the top 13 bits of
+// a Weyl sequence in a, so the 19 directions of a node take spread values.
+__host__ __device__ constexpr uint32_t sr_dither(uint32_t nh, int a) { return (nh + (uint32_t)a * 0x9E3779B9u) >> 19; }
+// x rounded stochastically to binary16: the dither added to the 13 bits that
+// the conversion drops (for a result in binary16's normal range), then
+// truncation toward zero, so the magnitude rounds up with probability equal
+// to its fraction of a binary16 unit.
+__device__ inline _Float16 f16_stochastic(float x, uint32_t r) {
+    const float y = __uint_as_float(__float_as_uint(x) + r);
+    return __builtin_bit_cast(_Float16, (uint16_t)__builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(y, 0.0f)));
+}
+
+// x y rounded on its own: the empty asm makes the product opaque, so that
+// -ffp-contract=fast cannot fuse it into a following add (the pragma that
+// would say so is not honoured under that flag).
+__device__ inline double mul_rounded(double x, double y) {
+    double p = x * y;
+    asm volatile("" : "+v"(p));
+    return p;
+}
+
 // Precision-explicit math (no silent promotion of float to double).  The
 // FP32 path uses the hardware reciprocal and square root (about 1 ulp); the
 // FP64 path keeps correctly rounded division and square root.
@@ -407,10 +453,18 @@ template <class R> struct Pre {
 // s_k (m_eq,k - m_k) + (1 - s_k/2) S_k otherwise (Eq. (4)).
 // acc = sum_a w_a psi(x + e_a) e_a, so F_m = -G psi acc and
 // |F_m|^2 / psi^2 = G^2 |acc|^2 (no division by psi).
+//
+// DEV: f holds the deviations g_a = fbar_a - w_a rt from the rest state of a
+// reference density rt, with drho = sum_a g_a and rho = rt + drho.  The rest
+// state's moments are known exactly (rt for the density and energy rows, rt/9
+// for the three fourth-order rows, -11 rt and 3 rt for the orthogonal e and
+// eps rows, zero elsewhere), so the rows that hold them take their differences
+// from drho instead of subtracting two numbers of the size of rho; the other
+// rows are unchanged, and the update g* = g + Minv (m* - m) keeps the form.
 // ---------------------------------------------------------------------------
-template <class R, int OP>
+template <class R, int OP, bool DEV = false>
 __device__ inline void collide(R f[Q], R rho, R Fx, R Fy, R Fz, R acc2, const Phys<R> &P,
-                               R *uout = nullptr) {
+                               R *uout = nullptr, R drho = (R)0, R rt = (R)0) {
     Pre<R> pr;
     pr.build(f);
     const R inv_rho = r_rcp(rho);
@@ -438,7 +492,7 @@ __device__ inline void collide(R f[Q], R rho, R Fx, R Fy, R Fz, R acc2, const Ph
         R m4 = pr.a12 + pr.a34 + pr.a56 + (R)2 * (pr.s16 + pr.s17 + pr.s18);
         R m5 = (R)2 * pr.a12 - pr.a34 - pr.a56 + pr.s16 + pr.s17 - (R)2 * pr.s18;
         R m6 = pr.a34 - pr.a56 + pr.s16 - pr.s17;
-        dm[4] = P.s_e * (rho + rho * u2 - m4) + ce * (R)2 * Fu + P.ksig_e * acc2;
+        dm[4] = P.s_e * ((DEV ? drho : rho) + rho * u2 - m4) + ce * (R)2 * Fu + P.ksig_e * acc2;
         dm[5] = snu * (rho * ((R)2 * uxx - uyy - uzz) - m5) + cn * (R)2 * ((R)2 * Fux - Fuy - Fuz);
         dm[6] = snu * (rho * (uyy - uzz) - m6) + cn * (R)2 * (Fuy - Fuz);
         dm[7] = snu * (rho * ux * uy - pr.p7) + cn * (Fx * uy + Fy * ux);
@@ -454,7 +508,7 @@ __device__ inline void collide(R f[Q], R rho, R Fx, R Fy, R Fz, R acc2, const Ph
         dm[14] = P.s_q * (rz - pr.c14) + qz;
         dm[15] = P.s_q * (ry - pr.c15) + qy;
         // fourth order, Eq. (10)
-        const R phi = rho * (R)(1.0 / 9.0) * ((R)1 - (R)1.5 * u2);
+        const R phi = DEV ? (R)(1.0 / 9.0) * (drho - (R)1.5 * rho * u2) : rho * (R)(1.0 / 9.0) * ((R)1 - (R)1.5 * u2);
         const R k2 = cp * (R)2 * third;
         dm[16] = P.s_pi * (phi + third * rho * (uxx + uyy) - pr.s16) + k2 * (Fux + Fuy);
         dm[17] = P.s_pi * (phi + third * rho * (uxx + uzz) - pr.s17) + k2 * (Fux + Fuz);
@@ -487,8 +541,11 @@ __device__ inline void collide(R f[Q], R rho, R Fx, R Fy, R Fz, R acc2, const Ph
         const R Sxx = (R)2 * ((R)2 * Fux - Fuy - Fuz), Sww = (R)2 * (Fuy - Fuz);
         const R two3 = (R)(2.0 / 3.0);
         dm[0] = (R)0;
-        dm[1] = P.s_e * (rho * ((R)(-11) + (R)19 * u2) - e) + ce * (R)38 * Fu + (R)19 * P.ksig_e * acc2;
-        dm[2] = P.s_eps * (rho * (P.w_eps + P.w_epsj * u2) - eps) + cE * P.w_epsj2 * Fu - (R)16 * P.ksig_eps * acc2;
+        const R e_eq = DEV ? (R)(-11) * drho + (R)19 * rho * u2 : rho * ((R)(-11) + (R)19 * u2);
+        const R eps_eq = DEV ? P.w_eps * drho + (P.w_eps - (R)3) * rt + P.w_epsj * rho * u2
+                             : rho * (P.w_eps + P.w_epsj * u2);
+        dm[1] = P.s_e * (e_eq - e) + ce * (R)38 * Fu + (R)19 * P.ksig_e * acc2;
+        dm[2] = P.s_eps * (eps_eq - eps) + cE * P.w_epsj2 * Fu - (R)16 * P.ksig_eps * acc2;
         dm[3] = Fx;
         dm[4] = P.s_q * (-two3 * rho * ux - qxm) - cq * two3 * Fx;
         dm[5] = Fy;

@@ -97,10 +97,14 @@ struct PopBuf {
 // direction a comes from (x - e_a), i.e. plane z - e_az, or, across a
 // half-way bounce-back wall, from direction opp(a) at the node itself.
 // PB = bytes of one z-plane of one direction.
-template <int S, bool WALL>
+// DEV (F16N): f receives the deviations h_a 2^-e from w_a rt (exact), and
+// *rt the node's reference density.
+template <int S, bool WALL, bool DEV = false>
 __device__ inline void pull(const PopBuf &A, int nz, uint32_t PB, int z, const NbOff &o,
-                            const Phys<typename Storage<S>::R> &P, typename Storage<S>::R f[Q]) {
+                            const Phys<typename Storage<S>::R> &P, typename Storage<S>::R f[Q],
+                            float *rt = nullptr) {
     using ST = Storage<S>;
+    static_assert(!DEV || S == ST_F16N, "deviation pull is F16N only");
     const bool bot = WALL && z == 0;
     const bool top = WALL && z == nz - 1;
     const int zm = WALL ? (bot ? z : z - 1) : (z == 0 ? nz - 1 : z - 1);
@@ -109,11 +113,15 @@ __device__ inline void pull(const PopBuf &A, int nz, uint32_t PB, int z, const N
     // F16N: every population arriving here is stored against this node's
     // reference density (plane 19 at the node).
     NodeShift ns;
-    if constexpr (S == ST_F16N)
-        ns.set(nref_val((uint16_t)__builtin_amdgcn_raw_buffer_load_b16(A.of(19), (int)o.c, (int)A.so(19, pc),
-                                                                          LBM_BUF_AUX)));
+    if constexpr (S == ST_F16N) {
+        const float r = nref_val((uint16_t)__builtin_amdgcn_raw_buffer_load_b16(A.of(19), (int)o.c,
+                                                                                (int)A.so(19, pc), LBM_BUF_AUX));
+        if constexpr (DEV) *rt = r;
+        else ns.set(r);
+    }
     auto sh = [&](int d) {
-        if constexpr (S == ST_F16N) return ns(d);
+        if constexpr (DEV) return 0.0f;
+        else if constexpr (S == ST_F16N) return ns(d);
         else return P.sh(d);
     };
 #define LBM_LD(d, plane, off) ST::ldb(A.of(d), (off), A.so((d), (plane)), sh(d), P.hsi)
@@ -218,6 +226,37 @@ template <class R> __device__ inline R sum19(const R f[Q]) {
     Pre<R> pr;
     pr.build(f);
     return pr.rho(f[0]);
+}
+
+// F16N at an arbitrary node: the deviations h_a 2^-e from w_a rt (exact in
+// FP32) into g; returns the node's reference rt.
+template <bool WALL>
+__device__ inline float pull_dev_at(const uint16_t *__restrict__ A, const GridDesc &g, int x, int y, int z,
+                                    const Phys<float> &P, float g_[Q]) {
+    NbOff o;
+    o.set(x, wrapi(x - 1, g.nx), wrapi(x + 1, g.nx), y, wrapi(y - 1, g.ny), wrapi(y + 1, g.ny), g.nx,
+          (uint32_t)sizeof(uint16_t));
+    PopBuf pb;
+    pb.set(A, (size_t)g.N, planes_of(ST_F16N));
+    float rt;
+    pull<ST_F16N, WALL, true>(pb, g.nz, (uint32_t)((size_t)g.nx * g.ny * sizeof(uint16_t)), z, o, P, g_, &rt);
+    return rt;
+}
+
+// Density at an arbitrary node.  F16N: the node's reference plus the sum of
+// its deviations, the density the split step computes.
+template <int S, bool WALL>
+__device__ inline typename Storage<S>::R density_at(const typename Storage<S>::T *__restrict__ A, const GridDesc &g,
+                                                    int x, int y, int z, const Phys<typename Storage<S>::R> &P) {
+    using R = typename Storage<S>::R;
+    R f[Q];
+    if constexpr (S == ST_F16N) {
+        const float rt = pull_dev_at<WALL>(A, g, x, y, z, P, f);
+        return rt + sum19<R>(f);
+    } else {
+        pull_at<S, WALL>(A, g, x, y, z, P, f);
+        return sum19<R>(f);
+    }
 }
 
 // Interaction-force stencil of Eq. (15) on a psi ring: returns
@@ -806,10 +845,9 @@ template <> struct Out8<ST_F16S> {
                ((unsigned long long)__builtin_bit_cast(uint32_t, hi[a]) << 32);
     }
 };
-// F16N: the shift of each value is that of the node it is stored for.
+// F16N: values arrive rounded to binary16 (stochastically, by the collider).
 template <> struct Out8<ST_F16N> : Out8<ST_F16S> {
-    __device__ inline void put_sh(int k, int a, float v, float shh, float hs) {
-        const _Float16 h = (_Float16)fmaf(v, hs, -shh);
+    __device__ inline void set(int k, int a, _Float16 h) {
         if (k == 0) lo[a].x = h;
         else if (k == 1) lo[a].y = h;
         else if (k == 2) hi[a].x = h;
@@ -961,14 +999,13 @@ template <int S> __device__ inline void unpack8(const Wide8 &r, int k, const Phy
 #pragma unroll
     for (int a = 0; a < Q; ++a) f[a] = Lane8<S>::cvt(r.w[a], k, P.sh(a), P.hsi);
 }
-// F16N: node k's populations against its reference density, element k of
-// the group's reference word rw (plane 19 at the group).
-__device__ inline void unpack8n(const Wide8 &r, unsigned long long rw, int k, const Phys<float> &P, float f[Q]) {
-    NodeShift ns;
-    ns.set(nref_val((uint16_t)(rw >> (16 * k))));
+// F16N: node k's deviations g_a = h_a 2^-e from w_a rt (exact in FP32); rt
+// is element k of the group's reference word (plane 19 at the group).
+__device__ inline void unpack8n(const Wide8 &r, int k, const Phys<float> &P, float g[Q]) {
 #pragma unroll
-    for (int a = 0; a < Q; ++a) f[a] = Lane8<ST_F16N>::cvt(r.w[a], k, ns(a), P.hsi);
+    for (int a = 0; a < Q; ++a) g[a] = Lane8<ST_F16N>::cvt(r.w[a], k, 0.0f, P.hsi);
 }
+__device__ inline float ref_of(unsigned long long rw, int k) { return nref_val((uint16_t)(rw >> (16 * k))); }
 
 // z-march of a tile with four nodes per thread: tx nodes (a multiple of 4)
 // by ty rows, (tx / 4) * ty interior threads; the halo ring is pulled one
@@ -1189,6 +1226,14 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
     // Role by wave, read as wave-uniform so the roles are scalar branches.
     const bool puller = __builtin_amdgcn_readfirstlane(threadIdx.x) < SPLIT_ROLE;
     const int rid = puller ? threadIdx.x : threadIdx.x - SPLIT_ROLE;
+    // F16N: this step's rounding key, from the seed in A's tail word; the
+    // first tile passes seed + 1 on in B's (nothing in this launch reads it).
+    uint32_t key = 0;
+    if constexpr (NREF) {
+        const uint32_t seed = *reinterpret_cast<const uint32_t *>(A + (size_t)planes_of(S) * N);
+        key = sr_key(seed);
+        if (tile == 0 && threadIdx.x == 0) *reinterpret_cast<uint32_t *>(B + (size_t)planes_of(S) * N) = seed + 1;
+    }
 
     // This thread's group (either role): nodes x0 + NPT lx .. + NPT - 1 of row
     // ly.  A group starting at nx (a ragged last tile) supplies psi of the
@@ -1300,10 +1345,17 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
         for (int r = 0; r < HR; ++r) {
             if (halo[r]) {
                 R fh[Q];
-                pull<S, WALL>(bA, nz, PB, pw, oh[r], P, fh);
-                const R rh = sum19<R>(fh);
+                R rh;
+                if constexpr (NREF) {
+                    float rth;
+                    pull<S, WALL, true>(bA, nz, PB, pw, oh[r], P, fh, &rth);
+                    rh = rth + sum19<R>(fh);
+                    nsl[chl[r]] = nref_bits(rh);
+                } else {
+                    pull<S, WALL>(bA, nz, PB, pw, oh[r], P, fh);
+                    rh = sum19<R>(fh);
+                }
                 slot[chl[r]] = pseudo_psi<R>(P, rh);
-                if constexpr (NREF) nsl[chl[r]] = nref_bits(rh);
             }
         }
         fold8<S, WALL>(q, sm, nz, pw, wl, wr);
@@ -1315,15 +1367,19 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             R f[Q];
-            if constexpr (NREF) unpack8n(q, rw, k, P, f);
-            else unpack8<S>(q, k, P, f);
-            const R rho = sum19<R>(f);
-            const R psi = pseudo_psi<R>(P, rho);
-            if (need_in) {
-                slot[cin + k] = psi;
-                if constexpr (NREF) nsl[cin + k] = nref_bits(rho);
+            R rho;
+            if constexpr (NREF) {  // deviations; the density is rt + their sum, and rbuf keeps the sum
+                unpack8n(q, k, P, f);
+                const R drho = sum19<R>(f);
+                rho = ref_of(rw, k) + drho;
+                if (need_in) nsl[cin + k] = nref_bits(rho);
+                if (active) L.rbuf[bs][nb + k] = drho;
+            } else {
+                unpack8<S>(q, k, P, f);
+                rho = sum19<R>(f);
+                if (active) L.rbuf[bs][nb + k] = rho;
             }
-            if (active) L.rbuf[bs][nb + k] = rho;
+            if (need_in) slot[cin + k] = pseudo_psi<R>(P, rho);
         }
     };
     // Collider's share of the halo ring of plane p (RING2), round r.
@@ -1335,8 +1391,15 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
             return;
         }
         R fh[Q];
-        pull<S, WALL>(bA, nz, PB, zwrap(p), oh[r], P, fh);
-        const R rh = sum19<R>(fh);
+        R rh;
+        if constexpr (NREF) {
+            float rth;
+            pull<S, WALL, true>(bA, nz, PB, zwrap(p), oh[r], P, fh, &rth);
+            rh = rth + sum19<R>(fh);
+        } else {
+            pull<S, WALL>(bA, nz, PB, zwrap(p), oh[r], P, fh);
+            rh = sum19<R>(fh);
+        }
         const R psh = pseudo_psi<R>(P, rh);
         if (halo[r]) {
             slot[chl[r]] = psh;
@@ -1368,26 +1431,36 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             R f[Q];
-            if constexpr (NREF) unpack8n(q, rw, k, P, f);
+            if constexpr (NREF) unpack8n(q, k, P, f);
             else unpack8<S>(q, k, P, f);
             R ax, ay, az;
             psi_stencil<R>(lo, mid, hi, cin + k, SX, ax, ay, az);
-            const R rho = L.rbuf[bs][nb + k];
             const R mG_psi = -P.G * mid[cin + k];
-            collide<R, OP>(f, rho, mG_psi * ax + rho * P.gx, mG_psi * ay + rho * P.gy, mG_psi * az + rho * P.gz,
-                           ax * ax + ay * ay + az * az, P);
             if constexpr (NREF) {
+                // Deviations g from w_a rt (rt: the reference they were stored
+                // against), collided in that form; a value for node x' is stored
+                // as (g*_a + w_a (rt - rt'(x'))) 2^e, rt' this step's reference of
+                // x' (the node itself where the value comes back from a wall),
+                // rounded stochastically with the dither of this node and a.
+                // The difference of two binary16 references is exact in FP32.
+                const R rt = ref_of(rw, k), drho = L.rbuf[bs][nb + k];
+                const R rho = rt + drho;
+                const uint32_t nh = sr_node(key, ((uint32_t)c * (uint32_t)ny + (uint32_t)gy) * (uint32_t)nx +
+                                                     (uint32_t)(gx + k));
+                collide<R, OP, true>(f, rho, mG_psi * ax + rho * P.gx, mG_psi * ay + rho * P.gy,
+                                     mG_psi * az + rho * P.gz, ax * ax + ay * ay + az * az, P, nullptr, drho, rt);
 #pragma unroll
                 for (int a = 0; a < Q; ++a) {
                     const bool back = (ez(a) < 0 && bot) || (ez(a) > 0 && top);
                     const uint16_t *pl = back ? nmid : (ez(a) < 0 ? nlo : (ez(a) > 0 ? nhi : nmid));
                     const int pos = back ? cin + k : cin + k + ex(a) + ey(a) * SX;
-                    // rt w_a 2^e: the same bits as (rt w_a) 2^e, since 2^e is exact.  Written
-                    // as a fused multiply-add with a zero addend (the same single rounding
-                    // of a positive product) so that the binary16 rt enters it directly.
-                    out.put_sh(k, a, f[a], __builtin_fmaf(nref_val(pl[pos]), P.wh(a), 0.0f), P.hs);
+                    out.set(k, a, f16_stochastic(__builtin_fmaf(P.wh(a), rt - nref_val(pl[pos]), f[a] * P.hs),
+                                                 sr_dither(nh, a)));
                 }
             } else {
+                const R rho = L.rbuf[bs][nb + k];
+                collide<R, OP>(f, rho, mG_psi * ax + rho * P.gx, mG_psi * ay + rho * P.gy, mG_psi * az + rho * P.gz,
+                               ax * ax + ay * ay + az * az, P);
 #pragma unroll
                 for (int a = 0; a < Q; ++a) out.put(k, a, f[a], P);
             }
@@ -1661,9 +1734,7 @@ __global__ void k_wall_rho(const typename Storage<S>::T *__restrict__ A,
     const int rem = (int)(i - (long long)k * plane);
     const int x = rem % nx, y = rem / nx;
     const int z = k == 0 ? 0 : (k == 1 ? 1 : (k == 2 ? nz - 2 : nz - 1));
-    R f[Q];
-    pull_at<S, true>(A, g, x, y, z, P, f);
-    rho_w[i] = sum19<R>(f);
+    rho_w[i] = density_at<S, true>(A, g, x, y, z, P);
 }
 
 template <class R>
@@ -1700,9 +1771,7 @@ __global__ void k_psi_full(const typename Storage<S>::T *__restrict__ A,
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < g.N;
          i += (long long)gridDim.x * blockDim.x) {
         const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((long long)nx * ny));
-        R f[Q];
-        pull_at<S, WALL>(A, g, x, y, z, P, f);
-        psi[i] = pseudo_psi<R>(P, sum19<R>(f));
+        psi[i] = pseudo_psi<R>(P, density_at<S, WALL>(A, g, x, y, z, P));
     }
 }
 
@@ -1718,13 +1787,16 @@ __device__ inline void node_macro(const typename Storage<S>::T *__restrict__ A,
     using R = typename Storage<S>::R;
     const int nx = g.nx, ny = g.ny;
     R f[Q];
-    pull_at<S, WALL>(A, g, x, y, z, P, f);
+    R rt = (R)0;  // F16N: f holds the deviations from w_a rt
+    if constexpr (S == ST_F16N) rt = pull_dev_at<WALL>(A, g, x, y, z, P, f);
+    else pull_at<S, WALL>(A, g, x, y, z, P, f);
     finite = true;
 #pragma unroll
     for (int a = 0; a < Q; ++a) finite = finite && isfinite(f[a]);
     Pre<R> pr;
     pr.build(f);
-    rho = pr.rho(f[0]);
+    if constexpr (S == ST_F16N) rho = rt + pr.rho(f[0]);
+    else rho = pr.rho(f[0]);
     j[0] = pr.jx();
     j[1] = pr.jy();
     j[2] = pr.jz();
@@ -1782,9 +1854,15 @@ __global__ void k_read_pops(const typename Storage<S>::T *__restrict__ A, double
          i += (long long)gridDim.x * blockDim.x) {
         const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((long long)nx * ny));
         R v[Q];
-        pull_at<S, WALL>(A, g, x, y, z, P, v);
+        if constexpr (S == ST_F16N) {  // w_a rt + h_a 2^-e, each operation rounded once in FP64
+            const double rt = (double)pull_dev_at<WALL>(A, g, x, y, z, P, v);
 #pragma unroll
-        for (int a = 0; a < Q; ++a) f[(size_t)a * g.N + i] = (double)v[a];
+            for (int a = 0; a < Q; ++a) f[(size_t)a * g.N + i] = mul_rounded(wclass(a), rt) + (double)v[a];
+        } else {
+            pull_at<S, WALL>(A, g, x, y, z, P, v);
+#pragma unroll
+            for (int a = 0; a < Q; ++a) f[(size_t)a * g.N + i] = (double)v[a];
+        }
     }
 }
 
@@ -1836,20 +1914,62 @@ __device__ inline void scatter_node(typename Storage<S>::T *__restrict__ A, cons
     }
 }
 
+// F16N from FP64 populations (periodic x and y): the reference rt is the
+// node's density rounded to FP32 and then to binary16, and each value is
+// (f_a - w_a rt) 2^e rounded once to binary16, the product and the
+// difference taken in FP64 (each rounded once).
+template <bool WALL>
+__device__ inline void scatter_node_dev(uint16_t *__restrict__ A, const GridDesc &g, const Phys<float> &P, int x,
+                                        int y, int z, const double f[Q]) {
+    const uint16_t rb = nref_bits((float)sum19<double>(f));
+    A[(size_t)19 * g.N + ((size_t)z * g.ny + y) * g.nx + x] = rb;
+    const double rt = (double)nref_val(rb), hs = (double)P.hs;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+        int sz = z - ez(a);
+        size_t idx;
+        int d = a;
+        if (WALL && (sz < 0 || sz >= g.nz)) {
+            idx = ((size_t)z * g.ny + y) * g.nx + x;
+            d = opp(a);
+        } else {
+            sz = wrapi(sz, g.nz);
+            idx = ((size_t)sz * g.ny + wrapi(y - ey(a), g.ny)) * g.nx + wrapi(x - ex(a), g.nx);
+        }
+        const _Float16 h = (_Float16)((f[a] - mul_rounded(wclass(a), rt)) * hs);
+        A[(size_t)d * g.N + idx] = __builtin_bit_cast(uint16_t, h);
+    }
+}
+
+// A state written from outside the step starts its rounding seed at zero.
+template <int S> __device__ inline void reset_seed(typename Storage<S>::T *__restrict__ A, const GridDesc &g) {
+    if constexpr (tail_elems(S) > 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *reinterpret_cast<uint32_t *>(A + (size_t)planes_of(S) * g.N) = 0u;
+    }
+}
+
 template <int S, bool WALL>
 __global__ void k_write_pops(typename Storage<S>::T *__restrict__ A, const double *__restrict__ f, GridDesc g,
                              PhysD pd) {
     using R = typename Storage<S>::R;
     Phys<R> P;
     P.load(pd);
+    reset_seed<S>(A, g);
     const int nx = g.nx, ny = g.ny;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < g.N;
          i += (long long)gridDim.x * blockDim.x) {
         const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((long long)nx * ny));
-        R v[Q];
+        if constexpr (S == ST_F16N) {
+            double fd[Q];
 #pragma unroll
-        for (int a = 0; a < Q; ++a) v[a] = (R)f[(size_t)a * g.N + i];
-        scatter_node<S, WALL>(A, g, P, x, y, z, v);
+            for (int a = 0; a < Q; ++a) fd[a] = f[(size_t)a * g.N + i];
+            scatter_node_dev<WALL>(A, g, P, x, y, z, fd);
+        } else {
+            R v[Q];
+#pragma unroll
+            for (int a = 0; a < Q; ++a) v[a] = (R)f[(size_t)a * g.N + i];
+            scatter_node<S, WALL>(A, g, P, x, y, z, v);
+        }
     }
 }
 
@@ -1859,6 +1979,7 @@ __global__ void k_init_fields(typename Storage<S>::T *__restrict__ A, const doub
     using R = typename Storage<S>::R;
     Phys<R> P;
     P.load(pd);
+    reset_seed<S>(A, g);
     const int nx = g.nx, ny = g.ny;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < g.N;
          i += (long long)gridDim.x * blockDim.x) {
@@ -1911,6 +2032,7 @@ __global__ void k_init_droplets(typename Storage<S>::T *__restrict__ A, DropletS
     using R = typename Storage<S>::R;
     Phys<R> P;
     P.load(pd);
+    reset_seed<S>(A, g);
     const int nx = g.nx, ny = g.ny;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < g.N;
          i += (long long)gridDim.x * blockDim.x) {

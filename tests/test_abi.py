@@ -147,14 +147,17 @@ def test_make_params_mapping():
 
 def test_f16n_layout_and_limits():
     """F16N holds a twentieth plane (the reference densities) beside the 19
-    populations of 2 bytes, and runs the split step only: nx a multiple of 4,
-    walls only on z (batches of such runs too)."""
+    populations of 2 bytes, and the seed of its stochastic rounding after
+    them, and runs the split step only: nx a multiple of 4, walls only on z
+    (batches of such runs too)."""
     p = binding.lbm_params_default()
     p.storage = binding.STORAGE["f16s"]
     n16s = binding.lbm_workspace_bytes(p)
     p.storage = binding.STORAGE["f16n"]
     n16n = binding.lbm_workspace_bytes(p)
-    assert n16n - n16s == 2 * 32 ** 3 * 2  # one more plane of 2-byte values in each of the two buffers
+    # one more plane of 2-byte values and the 16-byte rounding seed in each of the two buffers (256-byte aligned)
+    assert n16n - n16s == 2 * ((20 * 32 ** 3 * 2 + 16 + 255) // 256 * 256 - 19 * 32 ** 3 * 2)
+    assert binding.population_bytes("f16n", 32 ** 3) == 20 * 32 ** 3 * 2 + 16
     n = ctypes.c_size_t(0)
     L = binding.lib()
     p.nx = 30

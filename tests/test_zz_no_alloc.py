@@ -44,7 +44,7 @@ def test_noalloc_step_bit_identical_to_context_step():
     for name, cfg, init, steps in _cases():
         print(f"[gpu] noalloc {name}: {steps} calls", flush=True)
         N = cfg["nx"] * cfg["ny"] * cfg["nz"]
-        nbytes = binding.planes(cfg["storage"]) * N * ELEM[cfg["storage"]]
+        nbytes = binding.population_bytes(cfg["storage"], N)
         ref_lat = Lattice(cfg)
         ref_lat.init_droplets(init["droplets"], init["rho_L"], init["rho_V"], init["W"])
         src = _raw(ref_lat, nbytes)
