@@ -63,15 +63,33 @@ enum { LBM_OP_NONORTH = 0, /* Eqs. (7)-(14), (16): the paper's model */
  * power-of-two factor only moves h into the normal range of binary16. */
 enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16S = 2, LBM_STORE_F16N = 3 };
 /* F16N (binary16 relative to the pulling node) stores every population that
- * arrives at node x as h_a = (fbar*_a - w_a rt(x)) * 2^f16_exp in binary16,
- * rounded as F16S, where rt(x) is the density of x at the step that wrote the
- * state (the sum of its 19 populations in FP32), itself rounded to binary16 and
- * kept in a twentieth plane: element 19 N + i of the state holds rt of node i.
- * The shift w_a rt(x) is one FP32 product.  A node's populations then differ
- * from their shifts only by what streaming and collision changed in one step,
- * instead of by the whole liquid-vapour density contrast of F16S.  rho_ref is
- * ignored.  F16N runs the split step only (nx a multiple of 4, walls only on
- * z; batches too); its step moves 40 instead of 38 values of 2 bytes per node. */
+ * arrives at node x as h_a in binary16, standing for the value
+ * w_a rt(x) + h_a 2^-f16_exp exactly, where rt(x) is the density of x at the
+ * step that wrote the state (the sum of its 19 populations in FP32), itself
+ * rounded to binary16 and kept in a twentieth plane: element 19 N + i of the
+ * state holds rt of node i.  A node's populations then differ from their
+ * shifts only by what streaming and collision changed in one step, instead of
+ * by the whole liquid-vapour density contrast of F16S.  rho_ref is ignored.
+ *   The step works on the deviations h_a 2^-f16_exp (exact in FP32) and the
+ * density rt + their sum; the rest state's moments enter the collision
+ * analytically.  Its stores round stochastically: the FP32 value of
+ * (fbar*_a - w_a rt(x)) 2^f16_exp gets a 13-bit dither added to its bits and
+ * is truncated toward zero to binary16, so a value rounds up with probability
+ * equal to its fraction of a binary16 unit and changes smaller than half a
+ * unit per step are kept in expectation instead of stagnating.  The dither
+ * hashes a 32-bit seed, the index of the node whose population is stored and
+ * the direction.  The seed sits after the planes (element 20 N, as a 32-bit
+ * word; the buffer holds 20 N + 8 elements): each step reads it from the
+ * source and writes seed + 1 to the destination, and lbm_init_fields,
+ * lbm_init_droplets and lbm_write_populations set it to 0, so results are
+ * deterministic and the same in plain launches, graph replays, batches and
+ * lbm_step_noalloc.
+ *   lbm_write_populations computes (f_a - w_a rt) 2^f16_exp in FP64 (the
+ * product and the difference each rounded once) and rounds it once to
+ * binary16 (to nearest); lbm_read_populations returns w_a rt + h_a
+ * 2^-f16_exp in FP64 (product and sum each rounded once).  F16N runs the split
+ * step only (nx a multiple of 4, walls only on z; batches too); its step moves
+ * 40 instead of 38 values of 2 bytes per node. */
 
 /* Pseudopotential form (text after Eq. (15)). */
 enum { LBM_PSI_SQRT_CS = 0, /* psi = sqrt(2 (p_EOS - rho/3) / G), C-S p_EOS, Eq. (58) */
@@ -187,8 +205,8 @@ typedef struct lbm_batch lbm_batch;
 void lbm_params_default(lbm_params *p);
 
 /* Device bytes needed by lbm_create for these parameters: two population
- * buffers of 19 N elements (20 N for F16N), a psi buffer of N, wall planes and diagnostics
- * partials, each 256-byte aligned. */
+ * buffers of 19 N elements (20 N + 8 for F16N), a psi buffer of N, wall planes
+ * and diagnostics partials, each 256-byte aligned. */
 lbm_status lbm_workspace_bytes(const lbm_params *p, size_t *bytes);
 
 /* Create a lattice on the current device.  dev_ws: device buffer of at least
@@ -235,7 +253,8 @@ lbm_status lbm_set_graph_steps(lbm_ctx *ctx, int32_t k);
  * memory.
  *   p: the lattice parameters (validated as by lbm_create).
  *   dev_src, dev_dst: distinct device buffers of 19 N storage elements each
- *     (20 N for F16N),
+ *     (20 N + 8 for F16N, whose seed word dev_src supplies and dev_dst
+ *     receives incremented),
  *     256-byte aligned, in the layout of the raw state (lbm_save_state):
  *     element a * N + i holds direction a of node i, in the storage format of
  *     p->storage; owned by the caller.  dev_src is read, dev_dst written.

@@ -14,11 +14,18 @@ sees exactly the storage error and nothing else.  Formats:
   reference follows every node, so h holds only what changed at the node
   during one step (the streaming of a moving or curved interface, the
   velocity moments and the non-equilibrium part) instead of the whole
-  liquid-vapour contrast.
+  liquid-vapour contrast.  This is the first form of F16N: the shift in
+  FP32, the loaded value rounded to FP32, stores rounded to nearest.
+* ``f16n_sr``: the library's F16N: exact loads (w_a rt + h 2^-E), each store
+  rounded stochastically with the step's dither (``round_trip_n_sr`` of
+  ``f16s_format``).  Rounding to nearest let values that change by less
+  than half a binary16 unit per step stagnate; the dither removes that bias.
 
 Run from the repository root (about 25 minutes on 8 threads at n = 64):
 
     python tests/study_storage_formats.py --n 64 --steps 50,100,200,400
+
+``--formats f16n_sr --merge`` adds formats to an existing results file.
 
 Writes ``results/storage_formats_emulated.json``: for every format and step
 the largest relative density error in the liquid and in the vapour of the
@@ -39,6 +46,7 @@ sys.path.insert(0, ROOT)
 
 import lbm_inputs as li  # noqa: E402
 from oracle import ref  # noqa: E402
+from tests import f16s_format as fmt  # noqa: E402
 
 # Lattice weights of D3Q19 (rest, six axis, twelve diagonal directions), in
 # the oracle's direction order.
@@ -60,7 +68,12 @@ def shifted(f, ref_rho, E):
     return to_f32(to_f16((to_f32(f) - shift) * 2.0 ** E) / 2.0 ** E + shift)
 
 
-def store(name, f, rho_prev, rho_l, rho_v, E):
+def store(name, f, rho_prev, rho_l, rho_v, E, cfg=None, seed=None):
+    """The state f after the storage of format `name`; seed: the step's
+    rounding seed (None: the initial write)."""
+    if name == "f16n_sr":
+        c = dict(cfg, f16_exp=E)
+        return fmt.round_trip_n(f, rho_prev, c) if seed is None else fmt.round_trip_n_sr(f, rho_prev, c, seed)
     if name == "f64":
         return f
     if name == "f32":
@@ -83,6 +96,7 @@ def main():
     ap.add_argument("--formats", default="f32,f16s,f16s_rho0,f16s_mid,f16n")
     ap.add_argument("--threads", type=int, default=8)
     ap.add_argument("--out", default=os.path.join(ROOT, "results", "storage_formats_emulated.json"))
+    ap.add_argument("--merge", action="store_true", help="keep the other formats of an existing --out file")
     a = ap.parse_args()
     n = a.n
     steps = [int(s) for s in a.steps.split(",")]
@@ -100,12 +114,12 @@ def main():
                      "scale_exponent": E, "steps": steps, "formats": {}}
     for name in ["f64"] + a.formats.split(","):
         t0 = time.time()
-        f = store(name, f0, f0.sum(0), rl, rv, E)
+        f = store(name, f0, f0.sum(0), rl, rv, E, cfg)
         done, rec = 0, {}
         for s in steps:
-            for _ in range(s - done):
+            for t in range(done, s):
                 rp = f.sum(0)
-                f = store(name, ref.step(p, f, 1), rp, rl, rv, E)
+                f = store(name, ref.step(p, f, 1), rp, rl, rv, E, cfg, seed=t)
             done = s
             rec[s] = f.sum(0).copy()
         runs[name] = rec
@@ -124,6 +138,12 @@ def main():
             print(f"  step {s}: liquid {rows[-1]['rho_max_rel_err_liquid']:.2e} vapour "
                   f"{rows[-1]['rho_max_rel_err_vapour']:.2e} mass {rows[-1]['mass_drift']:+.1e}", flush=True)
         out["formats"][name] = rows
+    if a.merge and os.path.exists(a.out):
+        with open(a.out) as fh:
+            old = json.load(fh)
+        if old.get("steps") == steps and old.get("scale_exponent") == E:
+            old["formats"].update(out["formats"])
+            out = old
     with open(a.out, "w") as fh:
         json.dump(out, fh, indent=1)
 
