@@ -108,10 +108,11 @@ def mix32(h):
 
 
 def dither(seed, src, a):
-    """13-bit dithers of direction a for the values of source nodes src."""
+    """13-bit dithers of direction a for the values of source nodes src: the
+    field at bit 7a mod 19 of the node's hash under the step's key."""
     key = mix32((int(seed) + 0x9E3779B9) & _M)
     nh = mix32(np.asarray(src, dtype=np.uint64) ^ key)
-    return ((nh + ((a * 0x9E3779B9) & _M)) & _M) >> 19
+    return (nh >> np.uint64((7 * a) % 19)) & 0x1FFF
 
 
 def f16_rtz(y):
