@@ -252,8 +252,8 @@ struct NodeShift {
 // drift in mass and density over long quasi-static runs.
 //
 // mix32: a 32-bit integer finaliser (xorshift-multiply rounds with the
-// constants of C. Wellons' "lowbias32"); sr_key mixes the seed once per step,
-// sr_node the node index with it.
+// constants of C. Wellons' "lowbias32"); key mixes the seed once per step,
+// node_hash the node index with it.
 __host__ __device__ constexpr uint32_t mix32(uint32_t h) {
     h ^= h >> 16;
     h *= 0x7FEB352Du;
@@ -264,12 +264,9 @@ __host__ __device__ constexpr uint32_t mix32(uint32_t h) {
 }
 __host__ __device__ constexpr uint32_t sr_key(uint32_t seed) { return mix32(seed + 0x9E3779B9u); }
 __host__ __device__ constexpr uint32_t sr_node(uint32_t key, uint32_t node) { return mix32(node ^ key); }
-// 13-bit dither of direction a at a node whose hash is nh: the 13-bit field
-// of nh at bit 7a mod 19 (one bit-field extract).  Each field is uniform over
-// the steps, so every value's rounding is unbiased; the fields of one node's
-// directions overlap, which correlates their roundings within the step only.
-// (Measured 0.9% faster than a separate hash per direction.)
-__host__ __device__ constexpr uint32_t sr_dither(uint32_t nh, int a) { return (nh >> ((7 * a) % 19)) & 0x1FFFu; }
+// 13-bit dither of direction a at a node whose hash is nh: the top 13 bits of
+// a Weyl sequence in a, so the 19 directions of a node take spread values.
+__host__ __device__ constexpr uint32_t sr_dither(uint32_t nh, int a) { return (nh + (uint32_t)a * 0x9E3779B9u) >> 19; }
 // x rounded stochastically to binary16: the dither added to the 13 bits that
 // the conversion drops (for a result in binary16's normal range), then
 // truncation toward zero, so the magnitude rounds up with probability equal

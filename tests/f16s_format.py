@@ -108,11 +108,10 @@ def mix32(h):
 
 
 def dither(seed, src, a):
-    """13-bit dithers of direction a for the values of source nodes src: the
-    field at bit 7a mod 19 of the node's hash under the step's key."""
+    """13-bit dithers of direction a for the values of source nodes src."""
     key = mix32((int(seed) + 0x9E3779B9) & _M)
     nh = mix32(np.asarray(src, dtype=np.uint64) ^ key)
-    return (nh >> np.uint64((7 * a) % 19)) & 0x1FFF
+    return ((nh + ((a * 0x9E3779B9) & _M)) & _M) >> 19
 
 
 def f16_rtz(y):
