@@ -146,6 +146,24 @@ def test_f16n_one_step_equals_format_emulation(name, op):
     _check_one_step(h1, want, w64.sum(0)[None, :], cfg)
 
 
+@pytest.mark.parametrize("name,tiles", [("wide_128x20x10", [(128, 8, 5), (64, 16, 3), (32, 8, 10)]),
+                                        ("walls_40x33x19_60deg", [(40, 8, 19), (16, 16, 5), (20, 4, 7)])])
+def test_f16n_tile_shapes_bit_identical(name, tiles):
+    """The state after 6 steps does not depend on the tile shape.  A node's
+    density is computed by the pulling waves from its stored halves when it
+    lies inside a tile and from its loaded deviations when it lies in a halo
+    ring, so this holds only if both sums round alike."""
+    cfg, init, p, f0 = _case(name)
+    states = []
+    for t in tiles:
+        lat = _lattice(cfg, f0, tile=t)
+        lat.step(6)
+        states.append(lat.save_state().cpu().numpy())
+        lat.close()
+    for t, st in zip(tiles[1:], states[1:]):
+        assert np.array_equal(st, states[0]), t
+
+
 def _o16n_and_exact(p, cfg, f0, checkpoints):
     """(emulated-format oracle states, the largest |stored value| each held,
     plain FP64 oracle states)."""
