@@ -1249,7 +1249,8 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
     if constexpr (NREF) {
         const uint32_t seed = *reinterpret_cast<const uint32_t *>(A + (size_t)planes_of(S) * N);
         key = sr_key(seed);
-        if (tile == 0 && threadIdx.x == 0) *reinterpret_cast<uint32_t *>(B + (size_t)planes_of(S) * N) = seed + 1;
+        if (tile == 0 && threadIdx.x == 0)  // the whole 16-byte tail, so that saved states are deterministic
+            *reinterpret_cast<uint4 *>(B + (size_t)planes_of(S) * N) = make_uint4(seed + 1, 0u, 0u, 0u);
     }
 
     // This thread's group (either role): nodes x0 + NPT lx .. + NPT - 1 of row
@@ -1972,7 +1973,8 @@ __device__ inline void scatter_node_dev(uint16_t *__restrict__ A, const GridDesc
 // A state written from outside the step starts its rounding seed at zero.
 template <int S> __device__ inline void reset_seed(typename Storage<S>::T *__restrict__ A, const GridDesc &g) {
     if constexpr (tail_elems(S) > 0) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) *reinterpret_cast<uint32_t *>(A + (size_t)planes_of(S) * g.N) = 0u;
+        if (blockIdx.x == 0 && threadIdx.x == 0)
+            *reinterpret_cast<uint4 *>(A + (size_t)planes_of(S) * g.N) = make_uint4(0u, 0u, 0u, 0u);
     }
 }
 
