@@ -271,9 +271,14 @@ __host__ __device__ constexpr uint32_t sr_dither(uint32_t nh, int a) { return (n
 // the conversion drops (for a result in binary16's normal range), then
 // truncation toward zero, so the magnitude rounds up with probability equal
 // to its fraction of a binary16 unit.
+__device__ inline float f16_dithered(float x, uint32_t r) { return __uint_as_float(__float_as_uint(x) + r); }
 __device__ inline _Float16 f16_stochastic(float x, uint32_t r) {
-    const float y = __uint_as_float(__float_as_uint(x) + r);
-    return __builtin_bit_cast(_Float16, (uint16_t)__builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(y, 0.0f)));
+    return __builtin_bit_cast(_Float16,
+                              (uint16_t)__builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(f16_dithered(x, r), 0.0f)));
+}
+// Two dithered values truncated to binary16 in one instruction (low half y0).
+__device__ inline uint32_t f16_trunc2(float y0, float y1) {
+    return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(y0, y1));
 }
 
 // x y rounded on its own: the empty asm makes the product opaque, so that

@@ -847,17 +847,18 @@ template <> struct Out8<ST_F16S> {
                ((unsigned long long)__builtin_bit_cast(uint32_t, hi[a]) << 32);
     }
 };
-// F16N: values arrive rounded to binary16 (stochastically, by the collider).
-// Out8<ST_F16N> places them into halves, for a loop over the group's nodes
-// that the compiler unrolls (constant k); Out8Rolled shifts node k's value into
-// bits 16k of the direction's word, for a loop kept rolled (k at run time).
-template <> struct Out8<ST_F16N> : Out8<ST_F16S> {
+// F16N: values arrive dithered in FP32 and are truncated toward zero to
+// binary16 (the stochastic rounding of the collider).  Out8<ST_F16N> keeps them
+// and truncates two nodes per instruction at the store, for a loop over the
+// group's nodes that the compiler unrolls (constant k); Out8Rolled truncates
+// each at once and shifts it into bits 16k of the direction's word, for a loop
+// kept rolled (k at run time).
+template <> struct Out8<ST_F16N> {
+    float y[Q][4];  // dithered FP32 values, truncated in pairs at the store
     __device__ inline void clear() {}
-    __device__ inline void set(int k, int a, _Float16 h) {
-        if (k == 0) lo[a].x = h;
-        else if (k == 1) lo[a].y = h;
-        else if (k == 2) hi[a].x = h;
-        else hi[a].y = h;
+    __device__ inline void set_dithered(int k, int a, float v) { y[a][k] = v; }
+    __device__ inline unsigned long long word(int a) const {
+        return (unsigned long long)f16_trunc2(y[a][0], y[a][1]) | ((unsigned long long)f16_trunc2(y[a][2], y[a][3]) << 32);
     }
 };
 struct Out8Rolled {
@@ -866,8 +867,9 @@ struct Out8Rolled {
 #pragma unroll
         for (int a = 0; a < Q; ++a) w[a] = 0;
     }
-    __device__ inline void set(int k, int a, _Float16 h) {
-        w[a] |= (unsigned long long)__builtin_bit_cast(uint16_t, h) << (16 * k);
+    __device__ inline void set_dithered(int k, int a, float v) {
+        w[a] |= (unsigned long long)(__builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(v, 0.0f)) & 0xFFFFu)
+                << (16 * k);
     }
     __device__ inline unsigned long long word(int a) const { return w[a]; }
 };
@@ -1483,8 +1485,8 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
                     const bool back = (ez(a) < 0 && bot) || (ez(a) > 0 && top);
                     const uint16_t *pl = back ? nmid : (ez(a) < 0 ? nlo : (ez(a) > 0 ? nhi : nmid));
                     const int pos = back ? cin + k : cin + k + ex(a) + ey(a) * SX;
-                    out.set(k, a, f16_stochastic(__builtin_fmaf(P.wh(a), rt - nref_val(pl[pos]), f[a] * P.hs),
-                                                 sr_dither(nh, a)));
+                    out.set_dithered(k, a, f16_dithered(__builtin_fmaf(P.wh(a), rt - nref_val(pl[pos]), f[a] * P.hs),
+                                                        sr_dither(nh, a)));
                 }
             } else {
                 const R rho = L.rbuf[bs][nb + k];
