@@ -1451,12 +1451,13 @@ __device__ inline void tile_split(const typename Storage<S>::T *__restrict__ A, 
         const uint16_t *nlo = nslot(c - 1), *nmid = nslot(c), *nhi = nslot(c + 1);
         const bool bot = WALL && c == 0, top = WALL && c == nz - 1;
         // The walled and orthogonal F16N kernels keep this loop rolled: one
-        // node's values live at a time.  Unrolled, they spill into the loop over
-        // planes, and a spill reload there waits for the previous plane's stores
-        // (the vector-memory counter counts stores too): the walled step took
-        // 1.09 ms instead of 0.83 ms on the 384 x 384 x 192 sessile lattice.
-        // The periodic non-orthogonal kernel unrolls without spilling, and
-        // rolled it measured 0.57 ms instead of 0.34 ms at 256^3.
+        // node's values live at a time.  Fully unrolled they spill into the loop
+        // over planes, where a spill reload also waits for the previous plane's
+        // stores (the vector-memory counter counts stores too), and the walled
+        // step took 1.09 ms instead of 0.83 ms on the 384 x 384 x 192 sessile
+        // lattice; unrolled by two (no reload in that loop) it took 1.04 ms.  The
+        // periodic non-orthogonal kernel unrolls without spilling, and rolled it
+        // measured 0.57 ms instead of 0.34 ms at 256^3.
         constexpr int KU = (NREF && (WALL || OP == OP_ORTH)) ? 1 : NPT;
         std::conditional_t<KU == 1, Out8Rolled, Out8<S>> out;
         if constexpr (NREF) out.clear();
