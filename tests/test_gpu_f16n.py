@@ -164,6 +164,27 @@ def test_f16n_tile_shapes_bit_identical(name, tiles):
         assert np.array_equal(st, states[0]), t
 
 
+def test_f16n_seed_counts_steps_through_graphs_and_state():
+    """The rounding seed after the planes is zero after a write, one more
+    after every step (plain launches and graph replays alike), the other 12
+    bytes of its word zero, and a saved state resumes with it."""
+    cfg, init, p, f0 = _case("droplet_32")
+    N = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    seed = lambda lat: lat.save_state()[40 * N:40 * N + 16].cpu().numpy().view(np.uint32)
+    lat = _lattice(cfg, f0)
+    assert list(seed(lat)) == [0, 0, 0, 0]
+    lat.set_graph_steps(3)
+    lat.step(7)
+    assert list(seed(lat)) == [7, 0, 0, 0]
+    st = lat.save_state()
+    lat.step(2)
+    after = lat.save_state()
+    lat.load_state(st).step(2)
+    assert torch.equal(lat.save_state(), after)
+    assert list(seed(lat)) == [9, 0, 0, 0]
+    lat.close()
+
+
 def _o16n_and_exact(p, cfg, f0, checkpoints):
     """(emulated-format oracle states, the largest |stored value| each held,
     plain FP64 oracle states)."""
