@@ -79,9 +79,10 @@ enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16S = 2, LBM_STORE_F16N 
  * unit per step are kept in expectation instead of stagnating.  The dither
  * hashes a 32-bit seed, the index of the node whose population is stored and
  * the direction.  The seed sits after the planes (element 20 N, as a 32-bit
- * word; the buffer holds 20 N + 8 elements): each step reads it from the
- * source and writes seed + 1 to the destination, and lbm_init_fields,
- * lbm_init_droplets and lbm_write_populations set it to 0, so results are
+ * word followed by 12 zero bytes; the buffer holds 20 N + 8 elements): each
+ * step reads it from the source and writes seed + 1 to the destination, and
+ * lbm_init_fields, lbm_init_droplets and lbm_write_populations set it to 0
+ * (so that a saved state holds no uninitialised bytes), so results are
  * deterministic and the same in plain launches, graph replays, batches and
  * lbm_step_noalloc.
  *   lbm_write_populations computes (f_a - w_a rt) 2^f16_exp in FP64 (the

@@ -38,14 +38,41 @@ def flags(extra=()):
             "-ffp-contract=fast", "-munsafe-fp-atomics", "-Wall", *extra]
 
 
+def code_text(src: str) -> str:
+    """C/C++ source without its comments, with every run of blank space made
+    one space: what the compiler sees of it.  String and character literals
+    are kept as written."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":  # literal: copy up to the matching unescaped quote
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            out.append(" ")
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def source_digest() -> str:
-    """SHA-256 (first 16 hex digits) over the kernel sources and the compiler
-    flags: identifies the code that a stored profile measured."""
+    """SHA-256 (first 16 hex digits) over the code of the kernel sources
+    (``code_text``: comments and layout do not count) and the compiler flags:
+    identifies the code that a stored profile measured."""
     import hashlib
     h = hashlib.sha256()
     for d in DEPS:
-        with open(d, "rb") as fh:
-            h.update(fh.read())
+        with open(d, encoding="utf-8") as fh:
+            h.update(code_text(fh.read()).encode())
     h.update(" ".join(flags()).encode())
     return h.hexdigest()[:16]
 

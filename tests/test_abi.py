@@ -187,3 +187,16 @@ def test_largest_lattice_accepted_next_rejected(storage, nz_max):
     p.nz = nz_max + 1
     assert binding.lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == -5
     assert "too large" in binding.lbm_last_error()
+
+
+def test_source_digest_counts_code_not_comments():
+    """The digest that ties stored profiles to the kernel sources sees their
+    code only: comments and layout do not change it, code does, and literals
+    that look like comments are code."""
+    from paper_1805_08643_amd.build import code_text
+    a = "int f(int x) {\n  return x + 1; // one more\n}\n"
+    b = "/* the same */ int f(int x)   { return x + 1; }"
+    c = "int f(int x) { return x + 2; }"
+    assert code_text(a) == code_text(b) != code_text(c)
+    assert code_text('const char *s = "a // b /* c";') == 'const char *s = "a // b /* c";'
+    assert code_text("char q = '\\'';  // quote") == "char q = '\\'';"
